@@ -1,0 +1,192 @@
+/*
+ * ara.h -- C ABI of libara, an MI355X (gfx950) engine for aggregate risk
+ * analysis with primary and secondary uncertainty (Varghese & Rau-Chaplin,
+ * WHPCF'13).
+ *
+ * The calls follow the paper's problem statement: the inputs are the Year
+ * Event Table (YET), the extended event loss tables (XELTs) with their
+ * financial terms I, and layers of a portfolio with occurrence/aggregate terms
+ * T (section 2.1); the output is the Year Loss Table (YLT, Algorithm 1,
+ * section 2.2) and the risk measures PML and TVaR derived from it (section 2.4).
+ *
+ * Conventions for every call:
+ *   - No C++ exception crosses this ABI.  Every call returns an ara_status;
+ *     ara_last_error() gives a human-readable detail of the last failure.
+ *   - Inputs are owned by the caller and copied on load; they may be freed as
+ *     soon as the call returns.  Handles belong to the context until freed or
+ *     until ara_destroy().
+ *   - Outputs are caller-allocated.  A device pointer (for example a torch
+ *     tensor's data_ptr()) makes the call asynchronous on the given stream; a
+ *     host pointer makes it synchronous.
+ *   - hip_stream is a hipStream_t; NULL is the HIP null (default) stream,
+ *     which is also torch's default stream.
+ *   - One context per host thread; calls on one context must not overlap.
+ *   - All validation happens at load time, so kernels never see bad data.
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ara_ctx ara_ctx;     /* opaque; owns all device memory it allocates */
+typedef int32_t ara_status;
+
+#define ARA_OK        0
+#define ARA_E_INVAL  (-1)   /* bad argument, non-finite value, mean <= 0, max <= mean,
+                               share outside [0,1], duplicate event in an ELT          */
+#define ARA_E_RANGE  (-2)   /* event id outside [0, catalog), or floor(N/RP) < 1      */
+#define ARA_E_NOMEM  (-3)   /* host allocation failed                                 */
+#define ARA_E_BUDGET (-4)   /* the context's HBM budget would be exceeded             */
+#define ARA_E_DEVICE (-5)   /* HIP runtime error; the context is unusable afterwards  */
+#define ARA_E_STATE  (-6)   /* unknown or freed handle, poisoned context              */
+
+typedef enum {
+    ARA_MODE_MEAN = 0,       /* primary uncertainty only: each loss is the XELT mean   */
+    ARA_MODE_PLAIN = 1,      /* secondary uncertainty, exact inverse Beta (section 3)  */
+    ARA_MODE_SURROGATE = 2   /* secondary uncertainty, MLP sampler with exact fallback */
+} ara_mode;
+
+/* Context on HIP device `device`.  hbm_budget_bytes caps the device memory the
+ * context may hold (0 = no cap); a load or run that would exceed it fails with
+ * ARA_E_BUDGET and changes nothing. */
+ara_status  ara_create(int device, uint64_t hbm_budget_bytes, ara_ctx **out);
+void        ara_destroy(ara_ctx *ctx);
+/* Detail of the last failure on ctx; owned by ctx, valid until the next call. */
+const char *ara_last_error(const ara_ctx *ctx);
+/* Device bytes currently held by ctx (tables, YETs, workspaces). */
+uint64_t    ara_bytes_in_use(const ara_ctx *ctx);
+
+/*
+ * Load a YET (section 2.1: trials of event occurrences in time order; the
+ * time stamps are implied by position).  event_ids: int32, host or device.
+ * trial_offsets == NULL: fixed length, trial i is event_ids[i*K .. i*K+K).
+ * Otherwise trial i is event_ids[trial_offsets[i] .. trial_offsets[i+1])
+ * (int64 [n_trials+1], host memory, non-decreasing, starting at 0) and
+ * events_per_trial is ignored.  Every id must lie in [0, catalog_size)
+ * (ARA_E_RANGE otherwise).  n_trials must be below 2^32.
+ */
+ara_status ara_load_yet(ara_ctx *ctx, const int32_t *event_ids, const int64_t *trial_offsets,
+                        int64_t n_trials, int32_t events_per_trial, int32_t catalog_size,
+                        int32_t *yet_handle);
+ara_status ara_free_yet(ara_ctx *ctx, int32_t yet_handle);
+
+/*
+ * One XELT (section 2.1): per entry the event id, mean loss mu_l, independent
+ * and correlated standard deviations sigma_I, sigma_C (sigma_c == NULL means
+ * all zero) and maximum loss max_l; plus the XELT's financial terms I, read as
+ * (deductible, limit, share) and applied as share*min(max(l - ded, 0), limit).
+ * All arrays are host memory.  Requirements (ARA_E_INVAL otherwise): distinct
+ * event ids in [0, catalog_size), 0 < mean < max_loss, sigmas >= 0 and finite,
+ * deductible >= 0, limit > 0 (+inf allowed), share in [0, 1].
+ */
+typedef struct {
+    int32_t n_entries;
+    const int32_t *event_id;
+    const double *mean;
+    const double *sigma_i;
+    const double *sigma_c;      /* NULL => 0 */
+    const double *max_loss;
+    double deductible;
+    double limit;               /* +inf allowed */
+    double share;
+} ara_elt_desc;
+
+/* Load n_elts XELTs; the per-entry Beta parameters (section 3.3) are derived on
+ * the device at load time.  elt_handles: out[n_elts]. */
+ara_status ara_load_elts(ara_ctx *ctx, int32_t catalog_size, const ara_elt_desc *elts,
+                         int32_t n_elts, int32_t *elt_handles);
+ara_status ara_free_elts(ara_ctx *ctx, const int32_t *elt_handles, int32_t n);
+
+/*
+ * A layer (section 2.1): a set of 1..64 loaded XELTs, in the order their
+ * losses are summed, and the layer terms T = (OccR, OccL, AggR, AggL) of
+ * section 2.3, applied as min(max(l - R, 0), L) per occurrence and to the
+ * trial's cumulative occurrence loss.  program_id keys the program-specific
+ * random numbers z_(Prog,E) of section 3.1.
+ */
+typedef struct {
+    int32_t n_elts;
+    const int32_t *elt_handles;
+    double occ_retention;
+    double occ_limit;           /* +inf allowed */
+    double agg_retention;
+    double agg_limit;           /* +inf allowed */
+    uint32_t program_id;
+} ara_layer_desc;
+
+/*
+ * Algorithm 1 for one layer over the whole YET: ylt_out[i] = year loss of
+ * trial i (float, n_trials entries).  The random numbers of section 3.1 are
+ * u_I = U(Philox4x32-10(key (seed, program_id), counter (trial, slot, j, 0)))
+ * with j the XELT's position in the layer, and, for sigma_C > 0,
+ * u_C = U(Philox4x32-10(key (seed, 0xFFFFFFFF), counter (trial, slot,
+ * 0xFFFFFFFF, 1))), first output word, U(w) = (2*(w>>9)+1)*2^-24.
+ * The result is a deterministic function of the inputs and seed: it does not
+ * depend on the stream, launch shape or what else runs on the device.
+ * max_occ_out (optional, NULL to skip) receives the largest occurrence loss
+ * net of occurrence terms per trial (the occurrence exceedance basis).
+ */
+ara_status ara_run_layer(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layer,
+                         ara_mode mode, uint32_t seed, float *ylt_out, void *hip_stream);
+ara_status ara_run_layer_ex(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layer,
+                            ara_mode mode, uint32_t seed, int64_t trial_begin, int64_t trial_end,
+                            float *ylt_out, float *max_occ_out, void *hip_stream);
+
+/*
+ * A batch of layers over one YET in one launch: each trial tile's event ids
+ * are read from HBM once and evaluated for every layer.  ylt_outs[l] receives
+ * layer l's YLT (device pointers only).
+ */
+ara_status ara_run_layers(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layers,
+                          int32_t n_layers, ara_mode mode, uint32_t seed,
+                          float *const *ylt_outs, void *hip_stream);
+
+/*
+ * PML and TVaR (section 2.4) of a YLT of n_trials floats (device or host):
+ * for each return period RP, k = floor(n_trials / RP) (ARA_E_RANGE if k < 1);
+ * PML = the k-th largest year loss; TVaR = the mean of the k largest, summed in
+ * FP64.  pml_out/tvar_out: host, n_rp doubles each; the call returns when they
+ * are written.  n_rp <= 16.
+ */
+ara_status ara_risk_measures(ara_ctx *ctx, const float *ylt, int64_t n_trials,
+                             const double *return_periods, int32_t n_rp,
+                             double *pml_out, double *tvar_out, void *hip_stream);
+
+/*
+ * Auxiliary device calls (the building blocks of ara_run_layer, exposed for
+ * per-draw checks and for labelling training data of the sampling surrogate).
+ *
+ * ara_philox_uniforms: out[i] = U(Philox4x32-10(counter ctr[4i..4i+3],
+ * key (key0, key1)) word 0), U(w) = (2*(w>>9)+1)*2^-24 (section 3.1's random
+ * numbers as this library generates them).  ctr: uint32 [4n]; out: float [n];
+ * host or device pointers (host => synchronous).
+ *
+ * ara_beta_quantile: x[i] = InvCDF_beta(u[i]; a[i], b[i]) (section 3.3), the
+ * plain inverse of the regularised incomplete beta that ara_run_layer uses,
+ * computed on the device.  a, b > 0 and 0 < u < 1 (ARA_E_INVAL otherwise when
+ * the arrays are host memory; device arrays are not inspected).  All four
+ * arrays are double [n], host or device (host => synchronous).
+ */
+/*
+ * Kernel timing: when enabled, ara_run_layer* record HIP events on their stream
+ * immediately around the launch of the layer kernel (table building and
+ * output copies excluded); ara_last_kernel_ms waits for the last such launch
+ * and returns its duration in milliseconds.
+ */
+ara_status ara_set_profiling(ara_ctx *ctx, int32_t enabled);
+ara_status ara_last_kernel_ms(ara_ctx *ctx, double *ms_out);
+
+ara_status ara_philox_uniforms(ara_ctx *ctx, const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1,
+                               float *out, void *hip_stream);
+ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
+                             double *x_out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARA_H */

@@ -1,0 +1,817 @@
+// ara_api.hip -- host half of libara: the C ABI declared in include/ara.h.
+//
+// The host side validates inputs, owns device memory, builds the small
+// per-call descriptors and launches the kernels of ara_kernels.hip; every
+// step of the simulation itself runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ara.h"
+#include "ara_internal.hpp"
+
+using namespace ara;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct YetRec {
+    bool live = false;
+    DevBuf ev, offs;
+    int64_t N = 0;
+    int32_t K = 0, C = 0;
+};
+
+struct EltRec {
+    bool live = false;
+    int32_t C = 0, n = 0;
+    bool has_corr = false;
+    DevBuf idx, ent, cw, mean;
+    double ded = 0, lim = 0, share = 0;
+};
+
+// Pinned host + device slot pair used to pass per-call descriptors.
+struct StageSlot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr size_t kStageBytes = 256 * 1024;
+constexpr int kStageSlots = 8;
+
+}  // namespace
+
+struct ara_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0, used = 0;
+    bool poisoned = false;
+    std::string err;
+    std::vector<YetRec> yets;
+    std::vector<EltRec> elts;
+    // grow-only workspaces
+    DevBuf ws_tab;        // layer tables
+    DevBuf ws_out;        // device staging for host outputs
+    DevBuf ws_sel;        // risk-measure state
+    DevBuf ws_in;         // device staging for host inputs
+    double* sel_host = nullptr;
+    StageSlot stage[kStageSlots];
+    int next_stage = 0;
+    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+    bool profiling = false;
+    bool have_timing = false;
+    hipEvent_t k_start = nullptr, k_stop = nullptr;
+};
+
+namespace {
+
+ara_status fail(ara_ctx* c, ara_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) {
+        c->err = buf;
+        if (st == ARA_E_DEVICE) c->poisoned = true;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, ARA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+ara_status dev_alloc(ara_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (c->budget && c->used + bytes > c->budget)
+        return fail(c, ARA_E_BUDGET, "HBM budget exceeded: %llu in use + %llu requested > %llu",
+                    (unsigned long long)c->used, (unsigned long long)bytes, (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return fail(c, ARA_E_BUDGET, "device out of memory allocating %llu bytes", (unsigned long long)bytes);
+    }
+    if (e != hipSuccess) return fail(c, ARA_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e));
+    b.bytes = bytes;
+    c->used += bytes;
+    return ARA_OK;
+}
+
+void dev_free(ara_ctx* c, DevBuf& b)
+{
+    if (b.p) {
+        (void)hipFree(b.p);
+        c->used -= b.bytes;
+    }
+    b.p = nullptr;
+    b.bytes = 0;
+}
+
+// Grow-only workspace: the old buffer is released only after the device is idle.
+ara_status ws_reserve(ara_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (b.bytes >= bytes) return ARA_OK;
+    HIPCHK(c, hipDeviceSynchronize());
+    dev_free(c, b);
+    return dev_alloc(c, b, bytes + bytes / 8);
+}
+
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
+ara_status begin_call(ara_ctx* c, hipStream_t s)
+{
+    if (c->poisoned) return fail(c, ARA_E_STATE, "context is unusable after a device error");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->have_last && c->last_stream != s) HIPCHK(c, hipStreamWaitEvent(s, c->last, 0));
+    return ARA_OK;
+}
+
+ara_status end_call(ara_ctx* c, hipStream_t s)
+{
+    HIPCHK(c, hipEventRecord(c->last, s));
+    c->last_stream = s;
+    c->have_last = true;
+    return ARA_OK;
+}
+
+// Copy a small host descriptor to device memory through a pinned slot.
+ara_status stage(ara_ctx* c, const void* src, size_t bytes, hipStream_t s, void** dev, StageSlot** slot_out)
+{
+    if (bytes > kStageBytes) return fail(c, ARA_E_INVAL, "descriptor too large (%zu bytes)", bytes);
+    StageSlot& sl = c->stage[c->next_stage];
+    c->next_stage = (c->next_stage + 1) % kStageSlots;
+    if (sl.pending) HIPCHK(c, hipEventSynchronize(sl.done));
+    std::memcpy(sl.host, src, bytes);
+    HIPCHK(c, hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+    *dev = sl.dev;
+    *slot_out = &sl;
+    return ARA_OK;
+}
+
+ara_status release_stage(ara_ctx* c, StageSlot* sl, hipStream_t s)
+{
+    HIPCHK(c, hipEventRecord(sl->done, s));
+    sl->pending = true;
+    return ARA_OK;
+}
+
+hipStream_t pick_stream(ara_ctx*, void* s) { return (hipStream_t)s; }
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+// Validate a layer and resolve its XELT handles.
+ara_status check_layer(ara_ctx* c, const YetRec& y, const ara_layer_desc* L, std::vector<const EltRec*>& out)
+{
+    if (!L) return fail(c, ARA_E_INVAL, "layer is NULL");
+    if (L->n_elts < 1 || L->n_elts > kMaxEltsPerLayer)
+        return fail(c, ARA_E_INVAL, "a layer holds 1..%d XELTs (got %d)", kMaxEltsPerLayer, L->n_elts);
+    if (!L->elt_handles) return fail(c, ARA_E_INVAL, "elt_handles is NULL");
+    const double t[4] = {L->occ_retention, L->occ_limit, L->agg_retention, L->agg_limit};
+    for (double v : t)
+        if (std::isnan(v) || v < 0) return fail(c, ARA_E_INVAL, "layer terms must be >= 0");
+    if (!is_finite(L->occ_retention) || !is_finite(L->agg_retention))
+        return fail(c, ARA_E_INVAL, "retentions must be finite");
+    out.clear();
+    for (int j = 0; j < L->n_elts; ++j) {
+        const int32_t h = L->elt_handles[j];
+        if (h < 0 || h >= (int32_t)c->elts.size() || !c->elts[h].live)
+            return fail(c, ARA_E_STATE, "unknown XELT handle %d", h);
+        const EltRec& e = c->elts[h];
+        if (e.C != y.C)
+            return fail(c, ARA_E_INVAL, "XELT %d has catalog %d, the YET %d", h, e.C, y.C);
+        for (const EltRec* p : out)
+            if (p == &e) return fail(c, ARA_E_INVAL, "XELT %d appears twice in a layer", h);
+        out.push_back(&e);
+    }
+    return ARA_OK;
+}
+
+float to_f(double v) { return std::isinf(v) ? INFINITY : (float)v; }
+
+struct LayerPlan {
+    std::vector<EltDev> elts;
+    LayerDev dev;
+    size_t total = 0;
+    bool has_corr = false;
+};
+
+void plan_layer(const ara_layer_desc* L, const std::vector<const EltRec*>& es, LayerPlan& p)
+{
+    p.elts.assign(es.size(), EltDev{});
+    std::memset(&p.dev, 0, sizeof p.dev);
+    p.total = 0;
+    p.has_corr = false;
+    for (size_t j = 0; j < es.size(); ++j) {
+        const EltRec& e = *es[j];
+        EltDev& d = p.elts[j];
+        d.idx = (const int32_t*)e.idx.p;
+        d.ent = (const EntryRec*)e.ent.p;
+        d.cw = (const float2*)e.cw.p;
+        d.mean = (const double*)e.mean.p;
+        d.ded = e.ded;
+        d.lim = e.lim;
+        d.share = e.share;
+        d.n = e.n;
+        p.total += (size_t)e.n;
+        p.has_corr |= e.has_corr;
+        p.dev.jt[j] = make_float4(to_f(e.ded), to_f(e.lim), (float)e.share, 0.0f);
+    }
+    p.dev.occR = to_f(L->occ_retention);
+    p.dev.occL = to_f(L->occ_limit);
+    p.dev.aggR = to_f(L->agg_retention);
+    p.dev.aggL = to_f(L->agg_limit);
+    p.dev.prog = L->program_id;
+    p.dev.J = (int32_t)es.size();
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace bytes for one layer's tables.
+size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
+{
+    if (mode == ARA_MODE_MEAN) return align256((size_t)C * 4);
+    size_t b = align256((size_t)C * 16) + 2 * align256((size_t)C * 4) + align256(scan_scratch_words(C) * 4) +
+               align256(p.total * sizeof(EntryRec));
+    if (p.has_corr) b += align256(p.total * 8);
+    return b;
+}
+
+// Build one layer's tables inside ws at `base`; fills p.dev table pointers.
+ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* base, const EltDev* elts_dev,
+                        hipStream_t s)
+{
+    const int32_t J = p.dev.J;
+    if (mode == ARA_MODE_MEAN) {
+        float* occ = (float*)base;
+        HIPCHK(c, launch_mean_table(C, J, elts_dev, p.dev.occR, p.dev.occL, occ, s));
+        p.dev.occ_tab = occ;
+        return ARA_OK;
+    }
+    char* q = base;
+    uint4* rows = (uint4*)q;
+    q += align256((size_t)C * 16);
+    uint32_t* cnt = (uint32_t*)q;
+    q += align256((size_t)C * 4);
+    uint32_t* off = (uint32_t*)q;
+    q += align256((size_t)C * 4);
+    uint32_t* scr = (uint32_t*)q;
+    q += align256(scan_scratch_words(C) * 4);
+    EntryRec* pent = (EntryRec*)q;
+    q += align256(p.total * sizeof(EntryRec));
+    float2* pcw = nullptr;
+    if (p.has_corr) {
+        pcw = (float2*)q;
+        q += align256(p.total * 8);
+    }
+    HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
+    HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
+    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, s));
+    p.dev.rows = rows;
+    p.dev.pent = pent;
+    p.dev.pcw = pcw;
+    return ARA_OK;
+}
+
+ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
+                    uint32_t seed, int64_t t0, int64_t t1, float* const* ylt_outs, float* const* omax_outs,
+                    void* hip_stream, bool allow_host_out)
+{
+    if (!c) return ARA_E_STATE;
+    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
+        return fail(c, ARA_E_INVAL, "unknown mode %d", (int)mode);
+    if (mode == ARA_MODE_SURROGATE) return fail(c, ARA_E_INVAL, "surrogate mode needs a loaded surrogate");
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live)
+        return fail(c, ARA_E_STATE, "unknown YET handle %d", yh);
+    if (n_layers < 1 || !layers || !ylt_outs) return fail(c, ARA_E_INVAL, "no layers or outputs");
+    const YetRec& y = c->yets[yh];
+    if (t0 < 0 || t1 > y.N || t0 > t1) return fail(c, ARA_E_RANGE, "trial range [%lld, %lld) outside [0, %lld)",
+                                                   (long long)t0, (long long)t1, (long long)y.N);
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+
+    std::vector<LayerPlan> plans((size_t)n_layers);
+    std::vector<const EltRec*> es;
+    size_t tab_total = 0;
+    bool has_corr = false;
+    int32_t maxJ = 0;
+    for (int32_t l = 0; l < n_layers; ++l) {
+        if ((st = check_layer(c, y, &layers[l], es))) return st;
+        plan_layer(&layers[l], es, plans[l]);
+        tab_total += table_bytes(mode, y.C, plans[l]);
+        has_corr |= plans[l].has_corr;
+        maxJ = std::max(maxJ, plans[l].dev.J);
+    }
+    const int64_t n = t1 - t0;
+    // host outputs go through a device staging buffer
+    std::vector<bool> host_out((size_t)n_layers, false), host_om((size_t)n_layers, false);
+    size_t out_bytes = 0;
+    for (int32_t l = 0; l < n_layers; ++l) {
+        if (!ylt_outs[l]) return fail(c, ARA_E_INVAL, "ylt output %d is NULL", l);
+        host_out[l] = !is_device_ptr(ylt_outs[l]);
+        if (omax_outs && omax_outs[l]) host_om[l] = !is_device_ptr(omax_outs[l]);
+        if ((host_out[l] || host_om[l]) && !allow_host_out)
+            return fail(c, ARA_E_INVAL, "batched runs need device output buffers");
+        out_bytes += (host_out[l] ? align256((size_t)n * 4) : 0) + (host_om[l] ? align256((size_t)n * 4) : 0);
+    }
+    if ((st = ws_reserve(c, c->ws_tab, tab_total))) return st;
+    if (out_bytes && (st = ws_reserve(c, c->ws_out, out_bytes))) return st;
+
+    // XELT descriptors of every layer, then tables, then the layer array
+    std::vector<EltDev> all_elts;
+    std::vector<size_t> first((size_t)n_layers);
+    for (int32_t l = 0; l < n_layers; ++l) {
+        first[l] = all_elts.size();
+        all_elts.insert(all_elts.end(), plans[l].elts.begin(), plans[l].elts.end());
+    }
+    void* elts_dev = nullptr;
+    StageSlot* sl1 = nullptr;
+    if ((st = stage(c, all_elts.data(), all_elts.size() * sizeof(EltDev), s, &elts_dev, &sl1))) return st;
+    char* tb = (char*)c->ws_tab.p;
+    char* ob = (char*)c->ws_out.p;
+    std::vector<LayerDev> devs((size_t)n_layers);
+    for (int32_t l = 0; l < n_layers; ++l) {
+        LayerPlan& p = plans[l];
+        if ((st = build_tables(c, mode, y.C, p, tb, (const EltDev*)elts_dev + first[l], s))) return st;
+        tb += table_bytes(mode, y.C, p);
+        if (host_out[l]) {
+            p.dev.ylt = (float*)ob;
+            ob += align256((size_t)n * 4);
+        } else {
+            p.dev.ylt = ylt_outs[l];
+        }
+        if (omax_outs && omax_outs[l]) {
+            if (host_om[l]) {
+                p.dev.omax = (float*)ob;
+                ob += align256((size_t)n * 4);
+            } else {
+                p.dev.omax = omax_outs[l];
+            }
+        }
+        devs[l] = p.dev;
+    }
+    void* layers_dev = nullptr;
+    StageSlot* sl2 = nullptr;
+    if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl2))) return st;
+    YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
+    if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
+    HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, (const LayerDev*)layers_dev,
+                            n_layers, maxJ, seed, s));
+    if (c->profiling) {
+        HIPCHK(c, hipEventRecord(c->k_stop, s));
+        c->have_timing = true;
+    }
+    if ((st = release_stage(c, sl1, s))) return st;
+    if ((st = release_stage(c, sl2, s))) return st;
+    bool sync = false;
+    for (int32_t l = 0; l < n_layers; ++l) {
+        if (host_out[l]) {
+            HIPCHK(c, hipMemcpyAsync(ylt_outs[l], devs[l].ylt, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+            sync = true;
+        }
+        if (omax_outs && omax_outs[l] && host_om[l]) {
+            HIPCHK(c, hipMemcpyAsync(omax_outs[l], devs[l].omax, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+            sync = true;
+        }
+    }
+    if ((st = end_call(c, s))) return st;
+    if (sync) HIPCHK(c, hipStreamSynchronize(s));
+    return ARA_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+ara_status ara_create(int device, uint64_t hbm_budget_bytes, ara_ctx** out)
+{
+    if (!out) return ARA_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return ARA_E_DEVICE;
+    }
+    ara_ctx* c = new (std::nothrow) ara_ctx();
+    if (!c) return ARA_E_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    c->stream = nullptr;     // loads run on the null stream and synchronise before returning
+    if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->last, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return ARA_E_DEVICE;
+    }
+    for (auto& sl : c->stage) {
+        if (hipHostMalloc(&sl.host, kStageBytes, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc(&sl.dev, kStageBytes) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+            ara_destroy(c);
+            return ARA_E_DEVICE;
+        }
+    }
+    if (hipHostMalloc((void**)&c->sel_host, 2 * kMaxRp * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->k_start) != hipSuccess || hipEventCreate(&c->k_stop) != hipSuccess) {
+        ara_destroy(c);
+        return ARA_E_DEVICE;
+    }
+    *out = c;
+    return ARA_OK;
+}
+
+void ara_destroy(ara_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto& y : c->yets) {
+        dev_free(c, y.ev);
+        dev_free(c, y.offs);
+    }
+    for (auto& e : c->elts) {
+        dev_free(c, e.idx);
+        dev_free(c, e.ent);
+        dev_free(c, e.cw);
+        dev_free(c, e.mean);
+    }
+    dev_free(c, c->ws_tab);
+    dev_free(c, c->ws_out);
+    dev_free(c, c->ws_sel);
+    dev_free(c, c->ws_in);
+    for (auto& sl : c->stage) {
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (c->sel_host) (void)hipHostFree(c->sel_host);
+    if (c->k_start) (void)hipEventDestroy(c->k_start);
+    if (c->k_stop) (void)hipEventDestroy(c->k_stop);
+    if (c->last) (void)hipEventDestroy(c->last);
+    delete c;
+}
+
+const char* ara_last_error(const ara_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+uint64_t ara_bytes_in_use(const ara_ctx* c) { return c ? c->used : 0; }
+
+ara_status ara_load_yet(ara_ctx* c, const int32_t* event_ids, const int64_t* trial_offsets, int64_t n_trials,
+                        int32_t events_per_trial, int32_t catalog_size, int32_t* yet_handle)
+{
+    if (!c) return ARA_E_STATE;
+    if (!yet_handle) return fail(c, ARA_E_INVAL, "yet_handle is NULL");
+    if (n_trials < 0 || n_trials >= ((int64_t)1 << 32)) return fail(c, ARA_E_INVAL, "n_trials must be in [0, 2^32)");
+    if (catalog_size <= 0) return fail(c, ARA_E_INVAL, "catalog_size must be positive");
+    int64_t total;
+    if (trial_offsets) {
+        if (trial_offsets[0] != 0) return fail(c, ARA_E_INVAL, "trial_offsets[0] must be 0");
+        for (int64_t i = 0; i < n_trials; ++i)
+            if (trial_offsets[i + 1] < trial_offsets[i]) return fail(c, ARA_E_INVAL, "trial_offsets must not decrease");
+        total = trial_offsets[n_trials];
+    } else {
+        if (events_per_trial < 0) return fail(c, ARA_E_INVAL, "events_per_trial must be >= 0");
+        total = n_trials * (int64_t)events_per_trial;
+    }
+    if (total > 0 && !event_ids) return fail(c, ARA_E_INVAL, "event_ids is NULL");
+    ara_status st = begin_call(c, c->stream);
+    if (st) return st;
+    YetRec y;
+    y.N = n_trials;
+    y.K = trial_offsets ? 0 : events_per_trial;
+    y.C = catalog_size;
+    if ((st = dev_alloc(c, y.ev, (size_t)total * 4))) return st;
+    if (trial_offsets) {
+        if ((st = dev_alloc(c, y.offs, (size_t)(n_trials + 1) * 8))) {
+            dev_free(c, y.ev);
+            return st;
+        }
+        HIPCHK(c, hipMemcpy(y.offs.p, trial_offsets, (size_t)(n_trials + 1) * 8, hipMemcpyHostToDevice));
+    }
+    if (total > 0) {
+        const hipMemcpyKind kind = is_device_ptr(event_ids) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        HIPCHK(c, hipMemcpyAsync(y.ev.p, event_ids, (size_t)total * 4, kind, c->stream));
+    }
+    // every id must be a catalog event (checked on the device, where the ids live)
+    if ((st = ws_reserve(c, c->ws_sel, 64 * 1024))) return st;
+    unsigned int* bad = (unsigned int*)c->ws_sel.p;
+    HIPCHK(c, hipMemsetAsync(bad, 0, sizeof(unsigned int), c->stream));
+    HIPCHK(c, launch_validate_ids((const int32_t*)y.ev.p, total, catalog_size, bad, c->stream));
+    unsigned int nbad = 0;
+    HIPCHK(c, hipMemcpyAsync(&nbad, bad, sizeof nbad, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((st = end_call(c, c->stream))) return st;
+    if (nbad) {
+        dev_free(c, y.ev);
+        dev_free(c, y.offs);
+        return fail(c, ARA_E_RANGE, "%u event ids outside [0, %d)", nbad, catalog_size);
+    }
+    y.live = true;
+    c->yets.push_back(y);
+    *yet_handle = (int32_t)c->yets.size() - 1;
+    return ARA_OK;
+}
+
+ara_status ara_free_yet(ara_ctx* c, int32_t h)
+{
+    if (!c) return ARA_E_STATE;
+    if (h < 0 || h >= (int32_t)c->yets.size() || !c->yets[h].live) return fail(c, ARA_E_STATE, "unknown YET %d", h);
+    HIPCHK(c, hipDeviceSynchronize());
+    dev_free(c, c->yets[h].ev);
+    dev_free(c, c->yets[h].offs);
+    c->yets[h].live = false;
+    return ARA_OK;
+}
+
+static ara_status validate_elt(ara_ctx* c, int32_t C, const ara_elt_desc& d, int j, std::vector<uint8_t>& seen)
+{
+    if (d.n_entries < 0) return fail(c, ARA_E_INVAL, "XELT %d: negative n_entries", j);
+    if (d.n_entries > 0 && (!d.event_id || !d.mean || !d.sigma_i || !d.max_loss))
+        return fail(c, ARA_E_INVAL, "XELT %d: NULL array", j);
+    if (!(d.share >= 0.0 && d.share <= 1.0)) return fail(c, ARA_E_INVAL, "XELT %d: share outside [0,1]", j);
+    if (!(d.deductible >= 0.0) || !is_finite(d.deductible)) return fail(c, ARA_E_INVAL, "XELT %d: bad deductible", j);
+    if (!(d.limit > 0.0)) return fail(c, ARA_E_INVAL, "XELT %d: limit must be > 0", j);
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int32_t r = 0; r < d.n_entries; ++r) {
+        const int32_t e = d.event_id[r];
+        if (e < 0 || e >= C) return fail(c, ARA_E_RANGE, "XELT %d entry %d: event %d outside [0,%d)", j, r, e, C);
+        if (seen[e]) return fail(c, ARA_E_INVAL, "XELT %d: event %d appears twice", j, e);
+        seen[e] = 1;
+        const double mu = d.mean[r], si = d.sigma_i[r], sc = d.sigma_c ? d.sigma_c[r] : 0.0, mx = d.max_loss[r];
+        if (!is_finite(mu) || !is_finite(si) || !is_finite(sc) || !is_finite(mx))
+            return fail(c, ARA_E_INVAL, "XELT %d entry %d: non-finite value", j, r);
+        if (!(mu > 0.0)) return fail(c, ARA_E_INVAL, "XELT %d entry %d: mean must be > 0", j, r);
+        if (!(mx > mu)) return fail(c, ARA_E_INVAL, "XELT %d entry %d: max_loss must exceed the mean", j, r);
+        if (si < 0.0 || sc < 0.0) return fail(c, ARA_E_INVAL, "XELT %d entry %d: negative sigma", j, r);
+    }
+    return ARA_OK;
+}
+
+ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_t n_elts, int32_t* handles)
+{
+    if (!c) return ARA_E_STATE;
+    if (C <= 0 || n_elts < 0 || (n_elts > 0 && (!elts || !handles)))
+        return fail(c, ARA_E_INVAL, "bad arguments to ara_load_elts");
+    ara_status st;
+    std::vector<uint8_t> seen((size_t)C);
+    for (int j = 0; j < n_elts; ++j)
+        if ((st = validate_elt(c, C, elts[j], j, seen))) return st;
+    if ((st = begin_call(c, c->stream))) return st;
+    for (int j = 0; j < n_elts; ++j) {
+        const ara_elt_desc& d = elts[j];
+        EltRec e;
+        e.C = C;
+        e.n = d.n_entries;
+        e.ded = d.deductible;
+        e.lim = d.limit;
+        e.share = d.share;
+        e.has_corr = false;
+        if (d.sigma_c)
+            for (int32_t r = 0; r < d.n_entries && !e.has_corr; ++r) e.has_corr = d.sigma_c[r] > 0.0;
+        const size_t n = (size_t)d.n_entries;
+        if ((st = dev_alloc(c, e.idx, (size_t)C * 4)) || (st = dev_alloc(c, e.ent, n * sizeof(EntryRec))) ||
+            (st = dev_alloc(c, e.mean, n * 8)) || (e.has_corr && (st = dev_alloc(c, e.cw, n * 8)))) {
+            dev_free(c, e.idx);
+            dev_free(c, e.ent);
+            dev_free(c, e.mean);
+            dev_free(c, e.cw);
+            return st;
+        }
+        // raw inputs: ids, sigma_i, sigma_c, max (the mean goes straight to its own buffer)
+        const size_t in_bytes = align256(n * 4) + 3 * align256(n * 8);
+        if ((st = ws_reserve(c, c->ws_in, in_bytes))) return st;
+        char* q = (char*)c->ws_in.p;
+        int32_t* ids = (int32_t*)q;
+        double* si = (double*)(q + align256(n * 4));
+        double* sc = (double*)(q + align256(n * 4) + align256(n * 8));
+        double* mx = (double*)(q + align256(n * 4) + 2 * align256(n * 8));
+        HIPCHK(c, hipMemsetAsync(e.idx.p, 0xFF, (size_t)C * 4, c->stream));
+        if (n) {
+            HIPCHK(c, hipMemcpyAsync(ids, d.event_id, n * 4, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(e.mean.p, d.mean, n * 8, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(si, d.sigma_i, n * 8, hipMemcpyHostToDevice, c->stream));
+            if (d.sigma_c) HIPCHK(c, hipMemcpyAsync(sc, d.sigma_c, n * 8, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(mx, d.max_loss, n * 8, hipMemcpyHostToDevice, c->stream));
+        }
+        HIPCHK(c, launch_elt_index(ids, d.n_entries, (int32_t*)e.idx.p, c->stream));
+        HIPCHK(c, launch_elt_prepare(d.n_entries, (const double*)e.mean.p, si, d.sigma_c ? sc : nullptr, mx,
+                                     (EntryRec*)e.ent.p, (float2*)e.cw.p, c->stream));
+        // the staging buffer is reused by the next XELT: wait for this one
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        e.live = true;
+        c->elts.push_back(e);
+        handles[j] = (int32_t)c->elts.size() - 1;
+    }
+    return end_call(c, c->stream);
+}
+
+ara_status ara_free_elts(ara_ctx* c, const int32_t* h, int32_t n)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 0 || (n > 0 && !h)) return fail(c, ARA_E_INVAL, "bad arguments to ara_free_elts");
+    for (int i = 0; i < n; ++i)
+        if (h[i] < 0 || h[i] >= (int32_t)c->elts.size() || !c->elts[h[i]].live)
+            return fail(c, ARA_E_STATE, "unknown XELT handle %d", h[i]);
+    HIPCHK(c, hipDeviceSynchronize());
+    for (int i = 0; i < n; ++i) {
+        EltRec& e = c->elts[h[i]];
+        dev_free(c, e.idx);
+        dev_free(c, e.ent);
+        dev_free(c, e.cw);
+        dev_free(c, e.mean);
+        e.live = false;
+    }
+    return ARA_OK;
+}
+
+ara_status ara_run_layer(ara_ctx* c, int32_t yh, const ara_layer_desc* layer, ara_mode mode, uint32_t seed,
+                         float* ylt_out, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
+    float* outs[1] = {ylt_out};
+    return run_impl(c, yh, layer, 1, mode, seed, 0, c->yets[yh].N, outs, nullptr, hip_stream, true);
+}
+
+ara_status ara_run_layer_ex(ara_ctx* c, int32_t yh, const ara_layer_desc* layer, ara_mode mode, uint32_t seed,
+                            int64_t trial_begin, int64_t trial_end, float* ylt_out, float* max_occ_out,
+                            void* hip_stream)
+{
+    float* outs[1] = {ylt_out};
+    float* om[1] = {max_occ_out};
+    return run_impl(c, yh, layer, 1, mode, seed, trial_begin, trial_end, outs, om, hip_stream, true);
+}
+
+ara_status ara_run_layers(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
+                          uint32_t seed, float* const* ylt_outs, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
+    return run_impl(c, yh, layers, n_layers, mode, seed, 0, c->yets[yh].N, ylt_outs, nullptr, hip_stream, false);
+}
+
+ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const double* rps, int32_t n_rp, double* pml,
+                             double* tvar, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (!ylt || !rps || !pml || !tvar || n_rp < 1 || n_rp > kMaxRp || n < 1)
+        return fail(c, ARA_E_INVAL, "bad arguments to ara_risk_measures");
+    uint32_t ks[kMaxRp];
+    for (int r = 0; r < n_rp; ++r) {
+        if (!(rps[r] > 0.0) || !is_finite(rps[r])) return fail(c, ARA_E_INVAL, "return period must be positive");
+        const double k = std::floor((double)n / rps[r]);
+        if (k < 1.0) return fail(c, ARA_E_RANGE, "floor(N/RP) < 1 for RP %g", rps[r]);
+        if (k > 4294967295.0) return fail(c, ARA_E_RANGE, "k too large");
+        ks[r] = (uint32_t)k;
+    }
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    const size_t sel_bytes = align256(kMaxRp * 256 * 4) + align256(2 * kMaxRp * 4) +
+                             align256(kSelectBlocks * kMaxRp * 8) + align256(2 * kMaxRp * 8);
+    const bool dev_in = is_device_ptr(ylt);
+    const size_t in_bytes = dev_in ? 0 : align256((size_t)n * 4);
+    if ((st = ws_reserve(c, c->ws_sel, sel_bytes + in_bytes))) return st;
+    char* q = (char*)c->ws_sel.p;
+    SelectWs ws;
+    ws.hist = (uint32_t*)q;
+    q += align256(kMaxRp * 256 * 4);
+    ws.state = (uint32_t*)q;
+    q += align256(2 * kMaxRp * 4);
+    ws.partial = (double*)q;
+    q += align256(kSelectBlocks * kMaxRp * 8);
+    ws.out = (double*)q;
+    q += align256(2 * kMaxRp * 8);
+    const float* y = ylt;
+    if (!dev_in) {
+        HIPCHK(c, hipMemcpyAsync(q, ylt, (size_t)n * 4, hipMemcpyHostToDevice, s));
+        y = (const float*)q;
+    }
+    HIPCHK(c, launch_risk_measures(y, n, ks, n_rp, ws, s));
+    HIPCHK(c, hipMemcpyAsync(c->sel_host, ws.out, 2 * (size_t)n_rp * 8, hipMemcpyDeviceToHost, s));
+    if ((st = end_call(c, s))) return st;
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int r = 0; r < n_rp; ++r) {
+        pml[r] = c->sel_host[2 * r];
+        tvar[r] = c->sel_host[2 * r + 1];
+    }
+    return ARA_OK;
+}
+
+ara_status ara_set_profiling(ara_ctx* c, int32_t enabled)
+{
+    if (!c) return ARA_E_STATE;
+    c->profiling = enabled != 0;
+    c->have_timing = false;
+    return ARA_OK;
+}
+
+ara_status ara_last_kernel_ms(ara_ctx* c, double* ms)
+{
+    if (!c) return ARA_E_STATE;
+    if (!ms) return fail(c, ARA_E_INVAL, "ms_out is NULL");
+    if (!c->have_timing) return fail(c, ARA_E_STATE, "no timed launch (enable profiling first)");
+    HIPCHK(c, hipEventSynchronize(c->k_stop));
+    float f = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&f, c->k_start, c->k_stop));
+    *ms = (double)f;
+    return ARA_OK;
+}
+
+ara_status ara_philox_uniforms(ara_ctx* c, const uint32_t* ctr, int64_t n, uint32_t key0, uint32_t key1, float* out,
+                               void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(c, ARA_E_INVAL, "bad arguments to ara_philox_uniforms");
+    if (n == 0) return ARA_OK;
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    const bool din = is_device_ptr(ctr), dout = is_device_ptr(out);
+    const size_t need = (din ? 0 : align256((size_t)n * 16)) + (dout ? 0 : align256((size_t)n * 4));
+    if (need && (st = ws_reserve(c, c->ws_in, need))) return st;
+    char* q = (char*)c->ws_in.p;
+    const uint32_t* dc = ctr;
+    float* dout_p = out;
+    if (!din) {
+        HIPCHK(c, hipMemcpyAsync(q, ctr, (size_t)n * 16, hipMemcpyHostToDevice, s));
+        dc = (const uint32_t*)q;
+        q += align256((size_t)n * 16);
+    }
+    if (!dout) dout_p = (float*)q;
+    HIPCHK(c, launch_philox_uniforms(dc, n, key0, key1, dout_p, s));
+    if (!dout) HIPCHK(c, hipMemcpyAsync(out, dout_p, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+    if ((st = end_call(c, s))) return st;
+    if (!din || !dout) HIPCHK(c, hipStreamSynchronize(s));
+    return ARA_OK;
+}
+
+ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n, double* x,
+                             void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 0 || (n > 0 && (!a || !b || !u || !x))) return fail(c, ARA_E_INVAL, "bad arguments to ara_beta_quantile");
+    if (n == 0) return ARA_OK;
+    const bool da = is_device_ptr(a), db = is_device_ptr(b), du = is_device_ptr(u), dx = is_device_ptr(x);
+    if (!da)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(a[i] > 0.0) || !is_finite(a[i])) return fail(c, ARA_E_INVAL, "a[%lld] must be > 0", (long long)i);
+    if (!db)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(b[i] > 0.0) || !is_finite(b[i])) return fail(c, ARA_E_INVAL, "b[%lld] must be > 0", (long long)i);
+    if (!du)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(u[i] > 0.0 && u[i] < 1.0)) return fail(c, ARA_E_INVAL, "u[%lld] must lie in (0,1)", (long long)i);
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    const size_t nb = align256((size_t)n * 8);
+    const size_t need = (da ? 0 : nb) + (db ? 0 : nb) + (du ? 0 : nb) + (dx ? 0 : nb);
+    if (need && (st = ws_reserve(c, c->ws_in, need))) return st;
+    char* q = (char*)c->ws_in.p;
+    const double* ptr[3] = {a, b, u};
+    const bool dev[3] = {da, db, du};
+    for (int i = 0; i < 3; ++i)
+        if (!dev[i]) {
+            HIPCHK(c, hipMemcpyAsync(q, ptr[i], (size_t)n * 8, hipMemcpyHostToDevice, s));
+            ptr[i] = (const double*)q;
+            q += nb;
+        }
+    double* xo = dx ? x : (double*)q;
+    HIPCHK(c, launch_beta_quantile(ptr[0], ptr[1], ptr[2], n, xo, s));
+    if (!dx) HIPCHK(c, hipMemcpyAsync(x, xo, (size_t)n * 8, hipMemcpyDeviceToHost, s));
+    if ((st = end_call(c, s))) return st;
+    if (need) HIPCHK(c, hipStreamSynchronize(s));
+    return ARA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+// ara_internal.hpp -- device-side descriptors shared by the HIP kernels and
+// the host half of libara (not part of the public ABI).
+#pragma once
+
+#include "ara_math.hpp"
+
+namespace ara {
+
+constexpr int kMaxEltsPerLayer = 64;
+constexpr int kMaxRp = 16;
+constexpr float kSigmaClamp = 0.999f;      // sigma_beta <= 0.999 * sigma_beta_max
+
+// A loaded XELT as the kernels see it.
+struct EltDev {
+    const int32_t* idx;     // [C] entry of each event, -1 if absent (direct-access table)
+    const EntryRec* ent;    // [n] Beta parameters per entry
+    const float2* cw;       // [n] (c_I, c_C) weights of section 3.2, or null if sigma_C == 0
+    const double* mean;     // [n] mean loss mu_l
+    double ded, lim, share; // financial terms I of the XELT
+    int32_t n;
+    int32_t pad;
+};
+
+// One layer of a run: its tables (built per run on the device) and terms.
+struct LayerDev {
+    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count}
+    const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
+    const float2* pcw;      // [sum n_j] combine weights, or null
+    const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
+    float* ylt;             // [trial_end - trial_begin]
+    float* omax;            // [trial_end - trial_begin] or null
+    float occR, occL, aggR, aggL;
+    uint32_t prog;
+    int32_t J;
+    int32_t pad0, pad1;
+    float4 jt[kMaxEltsPerLayer];   // per-XELT (deductible, limit, share, 0)
+};
+
+// A YET as the kernels see it.
+struct YetDev {
+    const int32_t* ev;      // event ids
+    const int64_t* offs;    // [N+1] or null for a fixed K
+    int64_t N;
+    int32_t K;
+    int32_t C;
+};
+
+// ---- launchers (ara_kernels.hip) ----
+hipError_t launch_elt_index(const int32_t* event_id, int32_t n, int32_t* idx, hipStream_t s);
+hipError_t launch_elt_prepare(int32_t n, const double* mean, const double* sig_i, const double* sig_c,
+                              const double* maxl, EntryRec* ent, float2* cw, hipStream_t s);
+hipError_t launch_validate_ids(const int32_t* ev, int64_t n, int32_t C, unsigned int* bad, hipStream_t s);
+hipError_t launch_layer_count(int32_t C, int32_t J, const EltDev* elts, uint4* rows, uint32_t* cnt, hipStream_t s);
+size_t scan_scratch_words(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, hipStream_t s);
+hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
+                             EntryRec* pent, float2* pcw, hipStream_t s);
+hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,
+                             float* occ_tab, hipStream_t s);
+hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
+                         const LayerDev* layers, int32_t n_layers, int32_t max_J, uint32_t seed,
+                         hipStream_t s);
+
+hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s);
+hipError_t launch_beta_quantile(const double* a, const double* b, const double* u, int64_t n, double* x, hipStream_t s);
+
+struct SelectWs {
+    uint32_t* hist;         // [kMaxRp][256]
+    uint32_t* state;        // [2*kMaxRp]: prefix key, remaining rank
+    double* partial;        // [kSelectBlocks][kMaxRp]
+    double* out;            // [2*kMaxRp]: pml, tvar
+};
+constexpr int kSelectBlocks = 256;
+hipError_t launch_risk_measures(const float* y, int64_t n, const uint32_t* k_host, int32_t n_rp,
+                                const SelectWs& ws, hipStream_t s);
+
+}  // namespace ara

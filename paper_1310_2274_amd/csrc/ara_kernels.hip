@@ -1,0 +1,648 @@
+// ara_kernels.hip -- gfx950 kernels of libara.
+//
+// Layout of the work (Algorithm 1 of Varghese & Rau-Chaplin, section 2.2):
+//   * one 64-lane wavefront per trial; the trial's event ids stream from HBM
+//     64 at a time (one coalesced 256-byte row per wave per chunk);
+//   * each event id gathers one 16-byte row of the layer table (which XELTs
+//     hold the event, where their entries sit) -- the tables are built per
+//     run in event-major order so one row replaces J direct-table probes;
+//   * the (event, XELT) hits of a chunk are compacted into an LDS queue with a
+//     wave prefix sum and drained 64 draws at a time, so the variable-cost
+//     inverse Beta runs on full waves rather than on one thread per trial;
+//   * per-event sums are formed in XELT order, the occurrence terms applied
+//     per event, and the trial's cumulative loss is a compensated (Neumaier)
+//     per-lane sum combined across lanes with TwoSum in a fixed butterfly, so
+//     every YLT value is a deterministic function of its trial.
+#include "ara_internal.hpp"
+
+namespace ara {
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ int wave_incl_scan(int v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// (hi, lo) compensated pair: error-free sum of the high parts, low parts added
+__device__ __forceinline__ void two_sum_merge(float& hi, float& lo, float ohi, float olo)
+{
+    const float s = hi + ohi;
+    const float bb = s - hi;
+    const float err = (hi - (s - bb)) + (ohi - bb);
+    hi = s;
+    lo = (lo + olo) + err;
+}
+
+__device__ __forceinline__ void neumaier_add(float& s, float& c, float x)
+{
+    const float t = s + x;
+    if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+}
+
+// Sum of (hi, lo) over the wave; every lane ends with the same pair.
+__device__ __forceinline__ void wave_sum_pair(float& hi, float& lo)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const float oh = __shfl_xor(hi, m, 64);
+        const float ol = __shfl_xor(lo, m, 64);
+        two_sum_merge(hi, lo, oh, ol);
+    }
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// ===========================================================================
+// Load-time kernels
+// ===========================================================================
+__global__ void k_elt_index(const int32_t* __restrict__ event_id, int32_t n, int32_t* __restrict__ idx)
+{
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) idx[event_id[r]] = r;
+}
+
+// Section 3.3 moment matching, per entry, in FP64.
+__global__ void k_elt_prepare(int32_t n, const double* __restrict__ mean, const double* __restrict__ sig_i,
+                              const double* __restrict__ sig_c, const double* __restrict__ maxl,
+                              EntryRec* __restrict__ ent, float2* __restrict__ cw)
+{
+    const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const double mu = mean[r], si = sig_i[r], sc = sig_c ? sig_c[r] : 0.0, mx = maxl[r];
+    const double s = si + sc;                                   // sigma = sigma_I + sigma_C
+    EntryRec E;
+    E.maxl = (float)mx;
+    if (s == 0.0) {
+        E.a = 0.0; E.b = 0.0; E.lnB = mu; E.us = 0.0f;
+    } else {
+        const double mub = mu / mx;                             // mu_beta
+        const double sbmax = sqrt(mub * (1.0 - mub));           // sigma_beta_max
+        const double sb = fmin(s / mx, (double)kSigmaClamp * sbmax);
+        const double nu = (sbmax / sb) * (sbmax / sb) - 1.0;
+        E.a = mub * nu;
+        E.b = (1.0 - mub) * nu;
+        E.lnB = log_beta(E.a, E.b);
+        const double ts = (E.a + 1.0) / (E.a + E.b + 2.0);
+        E.us = (float)beta_inc_lower(ts, E.a, E.b, E.lnB);
+    }
+    ent[r] = E;
+    if (cw) {
+        float2 w;
+        if (sc == 0.0) w = make_float2(1.0f, 0.0f);
+        else if (si == 0.0) w = make_float2(0.0f, 1.0f);
+        else {
+            const double wi = si / s, wc = sc / s, nrm = sqrt(wi * wi + wc * wc);
+            w = make_float2((float)(wi / nrm), (float)(wc / nrm));
+        }
+        cw[r] = w;
+    }
+}
+
+__global__ void k_validate_ids(const int32_t* __restrict__ ev, int64_t n, int32_t C, unsigned int* bad)
+{
+    unsigned int local = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t e = ev[i];
+        local += (e < 0 || e >= C) ? 1u : 0u;
+    }
+    if (local) atomicAdd(bad, local);
+}
+
+// ===========================================================================
+// Per-run layer tables
+// ===========================================================================
+__global__ void k_layer_count(int32_t C, int32_t J, const EltDev* __restrict__ elts, uint4* __restrict__ rows,
+                              uint32_t* __restrict__ cnt)
+{
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    uint64_t mask = 0;
+    for (int j = 0; j < J; ++j)
+        if (elts[j].idx[e] >= 0) mask |= (uint64_t)1 << j;
+    const uint32_t c = (uint32_t)__popcll(mask);
+    rows[e] = make_uint4((uint32_t)mask, (uint32_t)(mask >> 32), 0u, c);
+    cnt[e] = c;
+}
+
+__global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ elts, const uint32_t* __restrict__ off,
+                             uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw)
+{
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    uint4 r = rows[e];
+    uint32_t o = off[e];
+    r.z = o;
+    rows[e] = r;
+    uint64_t mask = (uint64_t)r.x | ((uint64_t)r.y << 32);
+    while (mask) {
+        const int j = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const EltDev& X = elts[j];
+        const int32_t i = X.idx[e];
+        pent[o] = X.ent[i];
+        if (pcw) pcw[o] = X.cw ? X.cw[i] : make_float2(1.0f, 0.0f);
+        ++o;
+    }
+}
+
+// Mean mode (primary uncertainty only): the loss of an event occurrence does
+// not depend on the trial, so its net-of-terms occurrence loss is tabulated.
+__global__ void k_mean_table(int32_t C, int32_t J, const EltDev* __restrict__ elts, double occR, double occL,
+                             float* __restrict__ occ_tab)
+{
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    double c = 0.0;
+    for (int j = 0; j < J; ++j) {
+        const EltDev& X = elts[j];
+        const int32_t i = X.idx[e];
+        if (i < 0) continue;
+        const double l = X.mean[i];
+        c += X.share * fmin(fmax(l - X.ded, 0.0), X.lim);
+    }
+    occ_tab[e] = (float)fmin(fmax(c - occR, 0.0), occL);
+}
+
+// ---- exclusive scan of uint32 counts (three passes) ----
+constexpr int kScanTile = 1024;      // elements per block, 256 threads x 4
+
+__device__ uint32_t block_excl_scan_256(uint32_t v, uint32_t* sh, uint32_t& total)
+{
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t o = t >= d ? sh[t - d] : 0u;
+        __syncthreads();
+        sh[t] += o;
+        __syncthreads();
+    }
+    total = sh[255];
+    const uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n,
+                             uint32_t* __restrict__ tile_sums)
+{
+    __shared__ uint32_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * 4;
+    uint32_t v[4];
+    uint32_t s = 0;
+    for (int i = 0; i < 4; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0u;
+        s += v[i];
+    }
+    uint32_t total;
+    uint32_t run = block_excl_scan_256(s, sh, total);
+    for (int i = 0; i < 4; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(uint32_t* __restrict__ tile_sums, int64_t n_tiles)
+{
+    __shared__ uint32_t sh[256];
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t v = i < n_tiles ? tile_sums[i] : 0u;
+        uint32_t total;
+        const uint32_t ex = block_excl_scan_256(v, sh, total);
+        if (i < n_tiles) tile_sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t* __restrict__ tile_sums)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] += tile_sums[i / kScanTile];
+}
+
+// ===========================================================================
+// The layer kernels
+// ===========================================================================
+constexpr int kWavesPerBlock = 4;
+constexpr int kChunk = 64;                   // event slots per compaction round
+constexpr int kRound = 16;                   // draws per slot per drain round
+constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
+
+__device__ __forceinline__ void trial_range(const YetDev& y, int64_t i, int64_t& row, int32_t& len)
+{
+    if (y.offs) {
+        row = y.offs[i];
+        len = (int32_t)(y.offs[i + 1] - row);
+    } else {
+        row = i * (int64_t)y.K;
+        len = y.K;
+    }
+}
+
+// Draw z for one (trial, slot, XELT) hit: section 3.1 uniforms, section 3.2
+// combination when the entry has a correlated part.
+template <bool HAS_CORR>
+__device__ __forceinline__ double draw_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed, uint32_t prog,
+                                         const float2* pcw, uint32_t pi)
+{
+    const double ui = (double)u01(philox_word0(trial, slot, j, 0u, seed, prog));
+    if (!HAS_CORR || !pcw) return ui;
+    const float2 w = pcw[pi];
+    if (w.y == 0.0f) return ui;
+    const double uc = (double)u01(philox_word0(trial, slot, 0xFFFFFFFFu, 1u, seed, 0xFFFFFFFFu));
+    if (w.x == 0.0f) return uc;
+    return normcdf((double)w.x * normcdfinv(ui) + (double)w.y * normcdfinv(uc));
+}
+
+template <bool HAS_CORR>
+__global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+                                                     const LayerDev* __restrict__ layers, int32_t n_layers,
+                                                     uint32_t seed)
+{
+    __shared__ uint32_t qbuf[kWavesPerBlock][2][kQueue];
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t trial = t0 + (int64_t)blockIdx.x * kWavesPerBlock + w;
+    if (trial >= t1) return;
+    uint32_t* qidx = qbuf[w][0];     // packed entry index, then the draw's net loss
+    uint32_t* qmeta = qbuf[w][1];    // slot within chunk | XELT position << 8
+
+    int64_t row;
+    int32_t len;
+    trial_range(y, trial, row, len);
+    const uint32_t tr = (uint32_t)trial;
+
+    for (int32_t l = 0; l < n_layers; ++l) {
+        const LayerDev& L = layers[l];
+        float S = 0.0f, Sc = 0.0f, omax = 0.0f;
+        for (int32_t base = 0; base < len; base += kChunk) {
+            const int32_t k = base + lane;
+            const bool valid = k < len;
+            uint4 r = make_uint4(0, 0, 0, 0);
+            if (valid) r = L.rows[y.ev[row + k]];
+            uint64_t mask = (uint64_t)r.x | ((uint64_t)r.y << 32);
+            const uint32_t off = r.z;
+            int remaining = (int)r.w;
+            int rank = 0;
+            float c = 0.0f;                  // this event's loss across XELTs
+            while (true) {
+                const int take = remaining < kRound ? remaining : kRound;
+                const int incl = wave_incl_scan(take);
+                const int total = __shfl(incl, 63, 64);
+                if (total == 0) break;
+                const int pos = incl - take;
+                for (int i = 0; i < take; ++i) {
+                    const int j = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    qidx[pos + i] = off + (uint32_t)(rank + i);
+                    qmeta[pos + i] = (uint32_t)lane | ((uint32_t)j << 8);
+                }
+                wave_sync();
+                for (int q = lane; q < total; q += 64) {
+                    const uint32_t pi = qidx[q];
+                    const uint32_t meta = qmeta[q];
+                    const uint32_t slot = (uint32_t)base + (meta & 63u);
+                    const uint32_t j = meta >> 8;
+                    const EntryRec E = L.pent[pi];
+                    const double z = draw_z<HAS_CORR>(tr, slot, j, seed, L.prog, L.pcw, pi);
+                    const float loss = sample_loss(z, E);
+                    const float4 jt = L.jt[j];
+                    const float net = jt.z * xl(loss, jt.x, jt.y);       // per-XELT terms
+                    qidx[q] = __float_as_uint(net);
+                }
+                wave_sync();
+                for (int i = 0; i < take; ++i) c += __uint_as_float(qidx[pos + i]);
+                rank += take;
+                remaining -= take;
+                wave_sync();
+            }
+            if (valid) {
+                const float o = xl(c, L.occR, L.occL);                 // occurrence terms
+                omax = fmaxf(omax, o);
+                neumaier_add(S, Sc, o);
+            }
+        }
+        wave_sum_pair(S, Sc);
+        omax = wave_max(omax);
+        if (lane == 0) {
+            const float Y = fminf(fmaxf((S - L.aggR) + Sc, 0.0f), L.aggL);   // aggregate terms
+            L.ylt[trial - t0] = Y;
+            if (L.omax) L.omax[trial - t0] = omax;
+        }
+    }
+}
+
+// Mean mode: stream the event ids (16-byte loads when the rows allow it) and
+// gather the tabulated occurrence loss; HBM-bound.
+__global__ __launch_bounds__(256) void k_layer_mean(YetDev y, int64_t t0, int64_t t1,
+                                                    const LayerDev* __restrict__ layers, int32_t n_layers)
+{
+    const int w = threadIdx.x >> 6;
+    const int lane = lane_id();
+    const int64_t trial = t0 + (int64_t)blockIdx.x * kWavesPerBlock + w;
+    if (trial >= t1) return;
+    int64_t row;
+    int32_t len;
+    trial_range(y, trial, row, len);
+    const bool vec = ((row & 3) == 0) && ((len & 3) == 0);
+    for (int32_t l = 0; l < n_layers; ++l) {
+        const LayerDev& L = layers[l];
+        const float* __restrict__ tab = L.occ_tab;
+        float S = 0.0f, Sc = 0.0f, omax = 0.0f;
+        if (vec) {
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(y.ev + row);
+            const int32_t n4 = len >> 2;
+#pragma unroll 4
+            for (int32_t q = lane; q < n4; q += 64) {
+                const v4i e = __builtin_nontemporal_load(v4 + q);
+                const float a = tab[e.x], b = tab[e.y], c = tab[e.z], d = tab[e.w];
+                neumaier_add(S, Sc, a);
+                neumaier_add(S, Sc, b);
+                neumaier_add(S, Sc, c);
+                neumaier_add(S, Sc, d);
+                omax = fmaxf(omax, fmaxf(fmaxf(a, b), fmaxf(c, d)));
+            }
+        } else {
+            for (int32_t k = lane; k < len; k += 64) {
+                const float a = tab[y.ev[row + k]];
+                neumaier_add(S, Sc, a);
+                omax = fmaxf(omax, a);
+            }
+        }
+        wave_sum_pair(S, Sc);
+        omax = wave_max(omax);
+        if (lane == 0) {
+            L.ylt[trial - t0] = fminf(fmaxf((S - L.aggR) + Sc, 0.0f), L.aggL);
+            if (L.omax) L.omax[trial - t0] = omax;
+        }
+    }
+}
+
+// ===========================================================================
+// PML / TVaR: radix select of the k-th largest year loss (four 8-bit digits of
+// an order-preserving key), then an FP64 sum of everything above it.
+// ===========================================================================
+__device__ __forceinline__ uint32_t order_key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_value(uint32_t k)
+{
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k);
+}
+
+struct KList {
+    uint32_t k[kMaxRp];
+};
+
+__global__ void k_rm_init(uint32_t* state, uint32_t* hist, KList ks, int32_t n_rp)
+{
+    const int t = threadIdx.x;
+    if (t < n_rp) {
+        state[2 * t] = 0u;            // key prefix found so far
+        state[2 * t + 1] = ks.k[t];   // rank still to find inside the prefix
+    }
+    for (int i = t; i < kMaxRp * 256; i += blockDim.x) hist[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_rm_hist(const float* __restrict__ y, int64_t n, int32_t n_rp, int shift,
+                                                 const uint32_t* __restrict__ state, uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t lh[kMaxRp][256];
+    for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) lh[i >> 8][i & 255] = 0u;
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t key = order_key(y[i]);
+        for (int r = 0; r < n_rp; ++r) {
+            const uint32_t pre = state[2 * r];
+            const bool match = (shift == 24) ? true : (((key ^ pre) >> (shift + 8)) == 0u);
+            if (match) atomicAdd(&lh[r][(key >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_rp * 256; i += blockDim.x) {
+        const uint32_t v = lh[i >> 8][i & 255];
+        if (v) atomicAdd(&hist[i], v);
+    }
+}
+
+__global__ void k_rm_pick(uint32_t* state, uint32_t* hist, int32_t n_rp, int shift)
+{
+    const int r = threadIdx.x;
+    if (r < n_rp) {
+        uint32_t need = state[2 * r + 1];
+        uint32_t cum = 0;
+        int d = 255;
+        for (; d > 0; --d) {
+            const uint32_t h = hist[r * 256 + d];
+            if (cum + h >= need) break;
+            cum += h;
+        }
+        state[2 * r] |= (uint32_t)d << shift;
+        state[2 * r + 1] = need - cum;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kMaxRp * 256; i += blockDim.x) hist[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void k_rm_tail(const float* __restrict__ y, int64_t n, int32_t n_rp,
+                                                 const uint32_t* __restrict__ state, double* __restrict__ partial)
+{
+    __shared__ double sh[kMaxRp][256];
+    double acc[kMaxRp];
+    uint32_t thr[kMaxRp];
+    for (int r = 0; r < kMaxRp; ++r) {
+        acc[r] = 0.0;
+        thr[r] = r < n_rp ? state[2 * r] : 0xFFFFFFFFu;
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = y[i];
+        const uint32_t key = order_key(v);
+#pragma unroll
+        for (int r = 0; r < kMaxRp; ++r)
+            if (key > thr[r]) acc[r] += (double)v;
+    }
+    for (int r = 0; r < n_rp; ++r) sh[r][threadIdx.x] = acc[r];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int r = 0; r < n_rp; ++r) sh[r][threadIdx.x] += sh[r][threadIdx.x + d];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < n_rp) partial[blockIdx.x * kMaxRp + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_rm_final(const uint32_t* __restrict__ state, const double* __restrict__ partial, int32_t nblk,
+                           KList ks, int32_t n_rp, double* __restrict__ out)
+{
+    const int r = threadIdx.x;
+    if (r >= n_rp) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += partial[b * kMaxRp + r];
+    const double v = (double)key_value(state[2 * r]);
+    const double k = (double)ks.k[r];
+    out[2 * r] = v;                                        // PML: the k-th largest
+    out[2 * r + 1] = (s + (double)state[2 * r + 1] * v) / k; // TVaR: mean of the k largest
+}
+
+// ===========================================================================
+// Auxiliary kernels: uniforms and quantiles for arbitrary inputs
+// ===========================================================================
+__global__ void k_philox_uniforms(const uint4* __restrict__ ctr, int64_t n, uint32_t k0, uint32_t k1,
+                                  float* __restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 c = ctr[i];
+    out[i] = u01(philox_word0(c.x, c.y, c.z, c.w, k0, k1));
+}
+
+__global__ void k_beta_quantile(const double* __restrict__ a, const double* __restrict__ b,
+                                const double* __restrict__ u, int64_t n, double* __restrict__ x)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    EntryRec E;
+    E.a = a[i];
+    E.b = b[i];
+    E.lnB = log_beta(E.a, E.b);
+    E.us = (float)beta_inc_lower((E.a + 1.0) / (E.a + E.b + 2.0), E.a, E.b, E.lnB);
+    E.maxl = 1.0f;
+    x[i] = inv_beta(u[i], E);
+}
+
+// ===========================================================================
+// Launchers
+// ===========================================================================
+hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_philox_uniforms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const uint4*)ctr, n, k0, k1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_quantile(const double* a, const double* b, const double* u, int64_t n, double* x, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_beta_quantile, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a, b, u, n, x);
+    return hipGetLastError();
+}
+
+static inline unsigned nblocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+hipError_t launch_elt_index(const int32_t* event_id, int32_t n, int32_t* idx, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_elt_index, dim3(nblocks(n, 256)), dim3(256), 0, s, event_id, n, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_elt_prepare(int32_t n, const double* mean, const double* sig_i, const double* sig_c,
+                              const double* maxl, EntryRec* ent, float2* cw, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_elt_prepare, dim3(nblocks(n, 128)), dim3(128), 0, s, n, mean, sig_i, sig_c, maxl, ent, cw);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_ids(const int32_t* ev, int64_t n, int32_t C, unsigned int* bad, hipStream_t s)
+{
+    if (n > 0) {
+        const unsigned g = (unsigned)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_validate_ids, dim3(g), dim3(256), 0, s, ev, n, C, bad);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_layer_count(int32_t C, int32_t J, const EltDev* elts, uint4* rows, uint32_t* cnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_layer_count, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, rows, cnt);
+    return hipGetLastError();
+}
+
+size_t scan_scratch_words(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, hipStream_t s)
+{
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)tiles), dim3(256), 0, s, in, out, n, scratch);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(256), 0, s, scratch, tiles);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblocks(n, 256)), dim3(256), 0, s, out, n, (const uint32_t*)scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
+                             EntryRec* pent, float2* pcw, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL, float* occ_tab,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mean_table, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, occR, occL, occ_tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
+                         int32_t n_layers, int32_t /*max_J*/, uint32_t seed, hipStream_t s)
+{
+    const int64_t n = t1 - t0;
+    if (n <= 0 || n_layers <= 0) return hipSuccess;
+    const dim3 grid(nblocks(n, kWavesPerBlock)), block(64 * kWavesPerBlock);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_layer_mean, grid, block, 0, s, y, t0, t1, layers, n_layers);
+    else if (has_corr)
+        hipLaunchKernelGGL(k_layer_plain<true>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed);
+    else
+        hipLaunchKernelGGL(k_layer_plain<false>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_risk_measures(const float* y, int64_t n, const uint32_t* k_host, int32_t n_rp, const SelectWs& ws,
+                                hipStream_t s)
+{
+    KList ks{};
+    for (int r = 0; r < n_rp; ++r) ks.k[r] = k_host[r];
+    const int nblk = (int)std::min<int64_t>(kSelectBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(k_rm_init, dim3(1), dim3(256), 0, s, ws.state, ws.hist, ks, n_rp);
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_rm_hist, dim3(nblk), dim3(256), 0, s, y, n, n_rp, shift, (const uint32_t*)ws.state, ws.hist);
+        hipLaunchKernelGGL(k_rm_pick, dim3(1), dim3(256), 0, s, ws.state, ws.hist, n_rp, shift);
+    }
+    hipLaunchKernelGGL(k_rm_tail, dim3(nblk), dim3(256), 0, s, y, n, n_rp, (const uint32_t*)ws.state, ws.partial);
+    hipLaunchKernelGGL(k_rm_final, dim3(1), dim3(64), 0, s, (const uint32_t*)ws.state, (const double*)ws.partial, nblk,
+                       ks, n_rp, ws.out);
+    return hipGetLastError();
+}
+
+}  // namespace ara

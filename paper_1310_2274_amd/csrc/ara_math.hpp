@@ -1,0 +1,245 @@
+// ara_math.hpp -- device numerics for aggregate risk analysis with secondary
+// uncertainty on gfx950: counter-based uniforms, the log Beta function, the
+// regularised incomplete beta and its inverse (section 3.3 of Varghese &
+// Rau-Chaplin, WHPCF'13), and the normal transforms of section 3.2.
+//
+// Functions are __host__ __device__ so the same source can be exercised on
+// the host during development; the product path runs them on the GPU only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ara {
+
+// ---------------------------------------------------------------------------
+// Per-entry record of a loaded XELT, derived on the device at load time from
+// (mean, sigma_I + sigma_C, max_l) by the moment matching of section 3.3.
+// 32 bytes: one aligned vector load per draw.
+// ---------------------------------------------------------------------------
+struct alignas(16) EntryRec {
+    double a;      // alpha; 0 marks a degenerate entry (sigma = 0: loss = mean)
+    double b;      // beta
+    double lnB;    // ln B(alpha, beta); the mean loss for a degenerate entry
+    float us;      // I_ts(alpha, beta) at ts = (alpha+1)/(alpha+beta+2)
+    float maxl;    // max_l
+};
+static_assert(sizeof(EntryRec) == 32, "EntryRec must stay 32 bytes");
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32 -> 64-bit products; the key advances by the golden-ratio Weyl
+// constants between rounds.  Only the first output word is used here.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint32_t philox_word0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
+    constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)MA * c0;
+        const uint64_t pb = (uint64_t)MB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += WA;
+        k1 += WB;
+    }
+    return c0;
+}
+
+// 32-bit word -> odd multiple of 2^-24 in (0,1): exact in FP32, symmetric
+// about 1/2, never 0 or 1.
+__host__ __device__ inline float u01(uint32_t w)
+{
+    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// ln B(a, b).  lnGamma(b) - lnGamma(a+b) cancels badly when a << b, which is
+// exactly where the quantile is most sensitive (relative error / a), so the
+// difference D(a,b) = lnGamma(a+b) - lnGamma(b) is formed directly:
+//   D(a,b) = D(a,b+1) - log1p(a/b)                     (shift b to >= 16)
+//   D(a,b) = (b-1/2) log1p(a/b) + a ln(a+b) - a + w(a+b) - w(b)
+// with w the remainder of Stirling's series, w(z) = sum B_2k/(2k(2k-1) z^(2k-1)).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double stirling_remainder(double z)
+{
+    const double r = 1.0 / z, r2 = r * r;
+    return r * (1.0 / 12.0 + r2 * (-1.0 / 360.0 + r2 * (1.0 / 1260.0 + r2 * (-1.0 / 1680.0
+           + r2 * (1.0 / 1188.0 + r2 * (-691.0 / 360360.0 + r2 * (1.0 / 156.0)))))));
+}
+
+__host__ __device__ inline double lgamma_shift(double a, double b)
+{
+    double s = 0.0;
+    while (b < 16.0) {
+        s -= log1p(a / b);
+        b += 1.0;
+    }
+    const double c = a + b;
+    return s + (b - 0.5) * log1p(a / b) + a * log(c) - a + (stirling_remainder(c) - stirling_remainder(b));
+}
+
+__host__ __device__ inline double log_beta(double a, double b)
+{
+    const double s = a < b ? a : b, l = a < b ? b : a;
+    return lgamma(s) - lgamma_shift(s, l);
+}
+
+// ---------------------------------------------------------------------------
+// Continued fraction of the incomplete beta (DLMF 8.17.22):
+//   I_t(A,B) = t^A (1-t)^B / (A B(A,B)) / T,   T = 1 + d1/(1 + d2/(1 + ...))
+//   d_{2m+1} = -(A+m)(A+B+m) t / ((A+2m)(A+2m+1)),
+//   d_{2m}   =  m(B-m) t / ((A+2m-1)(A+2m)),
+// fast for t <= (A+1)/(A+B+2).  With d_n = p_n / q_n, q_n = (A+n-1)(A+n), the
+// equivalent fraction with partial denominators q_n and numerators q_{n-1} p_n
+// needs no division: the convergents follow X_n = q_n X_{n-1} + q_{n-1} p_n X_{n-2}
+// for numerators and denominators alike, rescaled by exact powers of two.
+// Returns T as num/den.
+// ---------------------------------------------------------------------------
+template <typename R>
+__host__ __device__ inline void beta_cf(R t, R A, R B, R eps, int max_pairs, R& num, R& den)
+{
+    R n2 = 1, n1 = 1;     // numerators   X_{-1}, X_0
+    R d2 = 0, d1 = 1;     // denominators X_{-1}, X_0
+    R qprev = 1;
+    const R apb = A + B;
+    for (int m = 0; m < max_pairs; ++m) {
+        const R fm = (R)m;
+        // n = 2m+1
+        const R qo = (A + 2 * fm) * (A + 2 * fm + 1);
+        const R po = -(A + fm) * (apb + fm) * t;
+        const R co = qprev * po;
+        const R no = qo * n1 + co * n2;
+        const R dd = qo * d1 + co * d2;
+        // n = 2m+2
+        const R qe = (A + 2 * fm + 1) * (A + 2 * fm + 2);
+        const R pe = (fm + 1) * (B - fm - 1) * t;
+        const R ce = qo * pe;
+        const R ne = qe * no + ce * n1;
+        const R de = qe * dd + ce * d1;
+        int ex;
+        frexp(fabs(de) > fabs(ne) ? de : ne, &ex);
+        n2 = ldexp(no, -ex);
+        d2 = ldexp(dd, -ex);
+        n1 = ldexp(ne, -ex);
+        d1 = ldexp(de, -ex);
+        qprev = qe;
+        const R x = n1 * d2, y = n2 * d1;
+        if (fabs(x - y) <= eps * fabs(x)) break;
+    }
+    num = n1;
+    den = d1;
+}
+
+// I_t(A, B) for t <= ~(A+1)/(A+B+2), FP64; lnB = ln B(A, B).
+__host__ __device__ inline double beta_inc_lower(double t, double A, double B, double lnB)
+{
+    if (t <= 0.0) return 0.0;
+    double num, den;
+    beta_cf<double>(t, A, B, 1e-16, 400, num, den);
+    return exp(A * log(t) + B * log1p(-t) - lnB) / A * (den / num);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse of the regularised incomplete beta: x with I_x(a,b) = z.
+//
+// The root lies below ts = (a+1)/(a+b+2) iff z <= us = I_ts(a,b) (stored per
+// entry).  Above it the reflection I_x(a,b) = 1 - I_{1-x}(b,a) turns the
+// problem into the same lower-tail one for t = 1-x, p = 1-z and swapped
+// shapes, so one solver covers both sides and the fraction always converges
+// quickly.  The solver works on y = ln t, where
+//   f(y) = ln I_t(A,B) - ln p = A y + B ln(1-t) - lnB - ln A - ln T - ln p,
+//   f'(y) = A T / (1 - t),
+// which is close to linear in the tails (I ~ t^A / (A B)), so Newton's method
+// converges in a few steps from the leading-term start y0 = (ln p + ln A +
+// lnB)/A even for shape parameters of 1e-6.  An FP32 stage brings y within
+// ~1e-3, then FP64 steps finish it (quadratic convergence): the FP64 pass is
+// what keeps tiny shapes, whose quantile amplifies any error in ln I by 1/A,
+// accurate to well below the YLT tolerance.
+// ---------------------------------------------------------------------------
+struct InvBetaStats {
+    int it32, it64;
+};
+
+__host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaStats* st = nullptr)
+{
+    const bool lower = z <= (double)E.us;
+    const double A = lower ? E.a : E.b;
+    const double B = lower ? E.b : E.a;
+    const double p = lower ? z : 1.0 - z;
+    const double lnB = E.lnB;
+
+    // ---- FP32 stage
+    const float Af = (float)A, Bf = (float)B;
+    const float lnpf = logf((float)p);
+    const float ts = (Af + 1.0f) / (Af + Bf + 2.0f);
+    const float ymax = logf(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    // the leading term and the constants are formed in FP64: for tiny A the
+    // two logs cancel to O(A) and the FP32 difference would be noise
+    const float c0f = (float)(-(lnB + log(A)));
+    float y = (float)((log(p) + log(A) + lnB) / A);
+    y = fmaxf(fminf(y, logf(ts)), -1e30f);
+    // below these t the loss rounds to 0 (lower side, FP32 loss) or x to 1
+    // (upper side, FP64): no need to iterate further
+    const float yfloor = lower ? -110.0f : -40.0f;
+    int it32 = 0;
+    for (; it32 < 12 && y > yfloor; ++it32) {
+        const float t = expf(y);
+        const float l1t = log1pf(-t);
+        float num, den;
+        beta_cf<float>(t, Af, Bf, 2e-7f, 48, num, den);
+        const float T = num / den;
+        const float f = Af * y + Bf * l1t + c0f - logf(T) - lnpf;
+        const float dy = -f * (1.0f - t) / (Af * T);
+        const float yn = fmaxf(fminf(y + dy, ymax), -1e30f);
+        const float step = yn - y;
+        y = yn;
+        if (fabsf(step) <= 2e-3f * fmaxf(1.0f, fabsf(y))) break;
+    }
+
+    // ---- FP64 polish
+    const double lnA = log(A), lnp = log(p);
+    const double ts64 = (A + 1.0) / (A + B + 2.0);
+    const double ymax64 = log(fmin(1.1 * ts64, 0.5 * (1.0 + ts64)));
+    double yd = (double)y;
+    int it64 = 0;
+    for (; it64 < 6 && yd > (double)yfloor; ++it64) {
+        const double t = exp(yd);
+        const double l1t = log1p(-t);
+        double num, den;
+        beta_cf<double>(t, A, B, 1e-15, 200, num, den);
+        const double T = num / den;
+        const double f = A * yd + B * l1t - lnB - lnA - log(T) - lnp;
+        const double dy = -f * (1.0 - t) / (A * T);
+        const double yn = fmax(fmin(yd + dy, ymax64), -1e300);
+        const double step = yn - yd;
+        yd = yn;
+        if (fabs(step) <= 1e-5) break;
+    }
+    if (st) {
+        st->it32 = it32;
+        st->it64 = it64;
+    }
+    return lower ? exp(yd) : -expm1(yd);
+}
+
+// Sampled loss of one draw: max_l * InvCDF_beta(z; alpha, beta) (section 3.3).
+__host__ __device__ inline float sample_loss(double z, const EntryRec& E)
+{
+    if (E.a == 0.0) return (float)E.lnB;       // degenerate: the mean loss
+    return E.maxl * (float)inv_beta(z, E);
+}
+
+// Financial terms: min(max(l - retention, 0), limit).
+__host__ __device__ inline float xl(float l, float retention, float limit)
+{
+    return fminf(fmaxf(l - retention, 0.0f), limit);
+}
+
+}  // namespace ara

@@ -1,0 +1,314 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs (section 2.2 Algorithm 1, sections 3.1-3.3, section 2.4)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1310_2274_amd as P
+from paper_1310_2274_amd import synth
+from gpu_helpers import assert_ylt_close, gpu_ylt, oracle_ylt, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    torch_cuda()
+    e = P.Engine(0)
+    yield e
+    e.close()
+
+
+# ------------------------------------------------------------ A3: uniforms
+def test_philox_uniforms_bit_exact(eng):
+    rng = np.random.default_rng(1)
+    n = 4096
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:8] = [[0, 0, 0, 0], [0xFFFFFFFF] * 4, [1, 2, 3, 4], [5, 0, 0, 0], [0, 5, 0, 0], [0, 0, 5, 0],
+               [0, 0, 0, 5], [7, 7, 7, 7]]
+    for key in [(0, 0), (1310, 3), (0xFFFFFFFF, 0xFFFFFFFF), (1310, 0xFFFFFFFF)]:
+        got = P.ara_philox_uniforms(eng.ctx, ctr, *key)
+        want = np.array([oracle.uniform(oracle.philox4x32_10(c, key)[0]) for c in ctr], dtype=np.float64)
+        assert np.array_equal(got.astype(np.float64), want)
+
+
+def test_uniforms_match_the_oracle_streams(eng):
+    # the exact counters the layer kernel uses: (trial, slot, j, 0) under (seed, program)
+    ctr = np.array([[t, s, j, 0] for t in (0, 5, 799999) for s in (0, 1, 999) for j in (0, 15, 63)], dtype=np.uint32)
+    got = P.ara_philox_uniforms(eng.ctx, ctr, 1310, 7)
+    want = [oracle.u_indep(1310, 7, int(c[0]), int(c[1]), int(c[2])) for c in ctr]
+    assert np.array_equal(got.astype(np.float64), np.array(want))
+    ctr = np.array([[t, s, 0xFFFFFFFF, 1] for t in (0, 9) for s in (0, 3)], dtype=np.uint32)
+    got = P.ara_philox_uniforms(eng.ctx, ctr, 1310, 0xFFFFFFFF)
+    assert np.array_equal(got.astype(np.float64), [oracle.u_corr(1310, int(c[0]), int(c[1])) for c in ctr])
+
+
+# ------------------------------------------------------------ A5/A6: inverse Beta
+def _grid(n, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(math.log(lo), math.log(hi), n))
+    b = np.exp(rng.uniform(math.log(lo), math.log(hi), n))
+    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    return a, b, u
+
+
+@pytest.mark.parametrize("lo,hi,seed", [(0.2, 50.0, 1), (1e-3, 40.0, 2), (3e-6, 35.0, 3)])
+def test_beta_quantile_vs_oracle(eng, lo, hi, seed):
+    a, b, u = _grid(20000, lo, hi, seed)
+    # and the closed-form corners
+    a[:4], b[:4], u[:4] = [1, 1, 0.5, 2], [3, 1, 0.5, 1], [0.5, 0.3, 0.3, 0.25]
+    x = P.ara_beta_quantile(eng.ctx, a, b, u)
+    xo = oracle.beta_inc_inv_vec(u, a, b, threads=0)
+    assert x[0] == pytest.approx(1 - 0.5 ** (1 / 3), rel=1e-12)
+    assert x[1] == pytest.approx(0.3, rel=1e-12)
+    assert x[2] == pytest.approx(math.sin(math.pi * 0.3 / 2) ** 2, rel=1e-12)
+    assert x[3] == pytest.approx(0.5, rel=1e-12)
+    visible = xo > 1e-30                 # below this the loss is 0 in FP32 on both sides
+    rel = np.abs(x[visible] - xo[visible]) / xo[visible]
+    assert np.all(rel <= 1e-8), (rel.max(), np.argmax(rel))
+    assert np.all(x[~visible] <= 1e-28)
+
+
+def test_beta_quantile_paper_scale_parameters(eng):
+    # (alpha, beta) from the section 3.3 moment matching of LogNormal losses
+    rng = np.random.default_rng(4)
+    n = 20000
+    mu = rng.lognormal(10, 1.5, n)
+    sd = mu * rng.uniform(0.5, 1.5, n)
+    mx = mu * rng.uniform(3, 10, n)
+    ab = np.array([oracle.beta_params(m, s, x)[:2] for m, s, x in zip(mu, sd, mx)])
+    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    x = P.ara_beta_quantile(eng.ctx, ab[:, 0], ab[:, 1], u)
+    xo = oracle.beta_inc_inv_vec(u, ab[:, 0], ab[:, 1])
+    visible = xo > 1e-30
+    assert np.max(np.abs(x[visible] - xo[visible]) / xo[visible]) <= 1e-8
+
+
+def test_beta_quantile_rejects_bad_input(eng):
+    with pytest.raises(P.AraError) as e:
+        P.ara_beta_quantile(eng.ctx, np.array([1.0]), np.array([-1.0]), np.array([0.5]))
+    assert e.value.status == P.ARA_E_INVAL
+    with pytest.raises(P.AraError):
+        P.ara_beta_quantile(eng.ctx, np.array([1.0]), np.array([1.0]), np.array([1.0]))
+
+
+# ------------------------------------------------------------ A1-A10: whole layer
+@pytest.mark.parametrize("mode", [oracle.MODE_MEAN, oracle.MODE_PLAIN])
+def test_tiny_workload_full_ylt(eng, mode):
+    wl = synth.tiny()
+    y, om, _ = gpu_ylt(eng, wl, mode, wl.seed, with_omax=True)
+    yo, g, omo = oracle_ylt(wl, np.arange(wl.n_trials), mode, wl.seed)
+    worst = assert_ylt_close(y, yo, g, f"tiny mode {mode}")
+    assert_ylt_close(om, omo, g, "max occurrence")
+    assert np.all(y >= 0) and np.all(y <= wl.layers[0].agg_limit * (1 + 1e-6))
+    print(f"tiny mode={mode}: worst |dY|/G = {worst:.3e}")
+
+
+@pytest.mark.parametrize("N,K,C,J,lo,hi,sc", [
+    (67, 1, 50, 1, 10, 30, 0.0),          # one event per trial
+    (130, 63, 400, 3, 50, 150, 0.0),      # chunk of 63 slots
+    (65, 65, 300, 17, 20, 60, 0.0),       # ragged chunk, > 16 draws per slot possible
+    (33, 130, 200, 40, 30, 120, 0.0),     # 40 XELTs: several drain rounds per slot
+    (40, 70, 120, 64, 40, 90, 0.0),       # 64 XELTs, dense hits
+    (50, 90, 500, 5, 100, 300, 0.6),      # correlated std (section 3.2 five steps)
+])
+def test_ragged_shapes(eng, N, K, C, J, lo, hi, sc):
+    wl = synth.custom(N, K, C, J, lo, hi, seed=N * 7 + J, sigma_c_frac=sc)
+    for mode in (oracle.MODE_MEAN, oracle.MODE_PLAIN):
+        y, om, _ = gpu_ylt(eng, wl, mode, 99, with_omax=True)
+        yo, g, omo = oracle_ylt(wl, np.arange(N), mode, 99)
+        assert_ylt_close(y, yo, g, f"N={N} K={K} J={J} mode={mode}")
+        assert_ylt_close(om, omo, g, "max occurrence")
+
+
+def test_degenerate_and_infinite_terms(eng):
+    wl = synth.custom(64, 40, 200, 4, 40, 80, seed=5)
+    lay = wl.layers[0]
+    lay.elts[0].sigma_i[::3] = 0.0                      # sigma = 0: loss is the mean
+    lay.elts[1].limit = math.inf
+    lay.elts[2].share = 0.0
+    lay.elts[3].share = 1.0
+    lay.occ_limit = math.inf
+    lay.agg_limit = math.inf
+    y, _ = gpu_ylt(eng, wl, oracle.MODE_PLAIN, 3)
+    yo, g, _ = oracle_ylt(wl, np.arange(64), oracle.MODE_PLAIN, 3)
+    assert_ylt_close(y, yo, g, "degenerate/inf")
+
+
+def test_variable_length_trials_and_empty_trials(eng):
+    torch = torch_cuda()
+    rng = np.random.default_rng(11)
+    N, C = 97, 300
+    lens = rng.integers(0, 150, N)
+    lens[[0, 5, 96]] = 0
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    ev = rng.integers(0, C, offs[-1], dtype=np.int32)
+    wl = synth.custom(N, 1, C, 6, 40, 120, seed=12)
+    yh = eng.load_yet(ev, C, trial_offsets=offs)
+    desc = eng.load_layer(wl.layers[0], C)
+    out = torch.empty(N, device="cuda")
+    P.ara_run_layer(eng.ctx, yh, desc, P.MODE_PLAIN, 5, out)
+    y = out.cpu().numpy().astype(np.float64)
+    for i in range(N):
+        row = ev[offs[i]:offs[i + 1]].reshape(1, -1)
+        if row.shape[1] == 0:
+            assert y[i] == 0.0
+            continue
+        yo, g, _ = oracle.run_layer(wl.layers[0], row, [i], C, 5)
+        assert_ylt_close(y[i:i + 1], yo, g, f"trial {i}")
+
+
+# ------------------------------------------------------------ paper scale (sampled)
+def test_paper_scale_sampled_trials(eng):
+    torch = torch_cuda()
+    wl = synth.paper_scale()
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    y, desc = gpu_ylt(eng, wl, oracle.MODE_PLAIN, wl.seed, yet_handle=yh)
+    rng = np.random.default_rng(2024)
+    trials = np.unique(np.concatenate([[0, 1, 63, 64, wl.n_trials - 1], rng.integers(0, wl.n_trials, 40)]))
+    yo, g, _ = oracle_ylt(wl, trials, oracle.MODE_PLAIN, wl.seed, threads=0)
+    worst = assert_ylt_close(y[trials], yo, g, "paper scale")
+    print(f"paper scale: worst |dY|/G = {worst:.3e} over {trials.size} trials")
+    # the aggregate clamps bind at this scale
+    assert 0.01 < np.mean(y == 0) < 0.99 and 0.01 < np.mean(y == np.float32(wl.layers[0].agg_limit)) < 0.99
+    # risk measures of the GPU YLT: exact order statistic, FP64 tail mean
+    rps = [10, 50, 100, 250]
+    pml, tvar = P.ara_risk_measures(eng.ctx, torch.from_numpy(y.astype(np.float32)).cuda(), rps)
+    po, to = oracle.risk_measures(y.astype(np.float32).astype(np.float64), rps)
+    assert np.array_equal(pml, po)
+    np.testing.assert_allclose(tvar, to, rtol=1e-12)
+    P.ara_free_yet(eng.ctx, yh)
+
+
+def test_mean_mode_paper_scale_sampled(eng):
+    wl = synth.paper_scale(n_trials=100_000)
+    y, _ = gpu_ylt(eng, wl, oracle.MODE_MEAN, wl.seed)
+    trials = np.arange(0, wl.n_trials, 997)
+    yo, g, _ = oracle_ylt(wl, trials, oracle.MODE_MEAN, wl.seed)
+    assert_ylt_close(y[trials], yo, g, "mean mode")
+
+
+# ------------------------------------------------------------ A11: PML / TVaR
+@pytest.mark.parametrize("n", [1, 10, 1000, 65537, 1_000_000])
+def test_risk_measures_vs_oracle(eng, n):
+    rng = np.random.default_rng(n)
+    y = rng.lognormal(10, 2, n).astype(np.float32)
+    if n > 100:
+        y[rng.integers(0, n, n // 10)] = 0.0            # ties at zero
+        y[rng.integers(0, n, n // 50)] = y[7]           # ties at an interior value
+    rps = [rp for rp in (1, 2, 10, 50, 100, 250, 1000) if math.floor(n / rp) >= 1]
+    pml, tvar = P.ara_risk_measures(eng.ctx, y, rps)
+    po, to = oracle.risk_measures(y.astype(np.float64), rps)
+    assert np.array_equal(pml, po)
+    np.testing.assert_allclose(tvar, to, rtol=1e-12)
+
+
+def test_risk_measures_hand_worked(eng):
+    from conftest import golden
+    w = golden("w2_risk.json")
+    pml, tvar = P.ara_risk_measures(eng.ctx, np.array(w["ylt"], dtype=np.float32), [c["rp"] for c in w["cases"]])
+    for c, p, t in zip(w["cases"], pml, tvar):
+        assert p == c["pml"] and t == c["tvar"]
+
+
+def test_risk_measures_errors(eng):
+    with pytest.raises(P.AraError) as e:
+        P.ara_risk_measures(eng.ctx, np.ones(10, dtype=np.float32), [11])
+    assert e.value.status == P.ARA_E_RANGE
+
+
+# ------------------------------------------------------------ determinism and batching
+def test_deterministic_and_range_invariant(eng):
+    torch = torch_cuda()
+    wl = synth.custom(1000, 200, 2000, 8, 100, 400, seed=41)
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    y1, desc = gpu_ylt(eng, wl, P.MODE_PLAIN, 9, yet_handle=yh)
+    y2, _ = gpu_ylt(eng, wl, P.MODE_PLAIN, 9, yet_handle=yh)
+    assert np.array_equal(y1, y2)
+    parts = []
+    for t0, t1 in [(0, 1), (1, 333), (333, 334), (334, 1000)]:
+        yp, _ = gpu_ylt(eng, wl, P.MODE_PLAIN, 9, yet_handle=yh, t0=t0, t1=t1)
+        parts.append(yp)
+    assert np.array_equal(np.concatenate(parts), y1)
+    # on another stream
+    s = torch.cuda.Stream()
+    out = torch.empty(wl.n_trials, device="cuda")
+    with torch.cuda.stream(s):
+        P.ara_run_layer(eng.ctx, yh, desc, P.MODE_PLAIN, 9, out, stream=s)
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.float64), y1)
+    # host output buffer
+    host = np.empty(wl.n_trials, dtype=np.float32)
+    P.ara_run_layer(eng.ctx, yh, desc, P.MODE_PLAIN, 9, host)
+    assert np.array_equal(host.astype(np.float64), y1)
+
+
+def test_batched_layers_equal_single_runs(eng):
+    torch = torch_cuda()
+    wl = synth.portfolio(n_layers=6, n_trials=3000)
+    wl.catalog_size = 100_000
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
+    for mode in (P.MODE_MEAN, P.MODE_PLAIN):
+        outs = [torch.empty(wl.n_trials, device="cuda") for _ in descs]
+        P.ara_run_layers(eng.ctx, yh, descs, mode, 17, outs)
+        torch.cuda.synchronize()
+        for d, o in zip(descs, outs):
+            single = torch.empty(wl.n_trials, device="cuda")
+            P.ara_run_layer(eng.ctx, yh, d, mode, 17, single)
+            torch.cuda.synchronize()
+            assert torch.equal(single, o)
+    # and the batch matches the oracle on a few trials of each layer
+    trials = np.array([0, 1, 1777, 2999])
+    outs = [torch.empty(wl.n_trials, device="cuda") for _ in descs]
+    P.ara_run_layers(eng.ctx, yh, descs, P.MODE_PLAIN, 17, outs)
+    torch.cuda.synchronize()
+    for l, o in enumerate(outs):
+        yo, g, _ = oracle.run_layer(wl.layers[l], wl.yet_rows(trials), trials, wl.catalog_size, 17)
+        assert_ylt_close(o.cpu().numpy()[trials].astype(np.float64), yo, g, f"batch layer {l}")
+
+
+# ------------------------------------------------------------ validation and budget
+def test_load_validation_errors(eng):
+    good = synth.custom(4, 4, 50, 1, 5, 10, seed=3).layers[0].elts[0]
+
+    def bad(**kw):
+        e = synth.ELT(good.event_id.copy(), good.mean.copy(), good.sigma_i.copy(), None, good.max_loss.copy(),
+                      good.deductible, good.limit, good.share)
+        for k, v in kw.items():
+            if k in ("mean", "max_loss", "sigma_i", "event_id"):
+                getattr(e, k)[0] = v
+            else:
+                setattr(e, k, v)
+        return e
+
+    cases = [(bad(mean=-1.0), P.ARA_E_INVAL), (bad(max_loss=1.0), P.ARA_E_INVAL), (bad(share=1.5), P.ARA_E_INVAL),
+             (bad(sigma_i=math.nan), P.ARA_E_INVAL), (bad(event_id=50), P.ARA_E_RANGE),
+             (bad(event_id=int(good.event_id[1])), P.ARA_E_INVAL), (bad(limit=0.0), P.ARA_E_INVAL)]
+    for e, status in cases:
+        with pytest.raises(P.AraError) as ex:
+            P.ara_load_elts(eng.ctx, 50, [e])
+        assert ex.value.status == status
+    with pytest.raises(P.AraError) as ex:
+        P.ara_load_yet(eng.ctx, np.array([[0, 1], [2, 50]], dtype=np.int32), 50)
+    assert ex.value.status == P.ARA_E_RANGE
+    h = P.ara_load_elts(eng.ctx, 50, [good])
+    yh = P.ara_load_yet(eng.ctx, np.zeros((3, 3), dtype=np.int32), 60)
+    with pytest.raises(P.AraError):     # catalog mismatch
+        P.ara_run_layer(eng.ctx, yh, P.layer_desc(h, 0, 1, 0, 1), P.MODE_PLAIN, 1, np.empty(3, np.float32))
+    with pytest.raises(P.AraError) as ex:
+        P.ara_run_layer(eng.ctx, 12345, P.layer_desc(h, 0, 1, 0, 1), P.MODE_PLAIN, 1, np.empty(3, np.float32))
+    assert ex.value.status == P.ARA_E_STATE
+
+
+def test_hbm_budget_refusal():
+    torch_cuda()
+    with P.Engine(0, hbm_budget_bytes=8 << 20) as e:
+        with pytest.raises(P.AraError) as ex:
+            P.ara_load_yet(e.ctx, np.zeros((4096, 1024), dtype=np.int32), 10)   # 16 MB > 8 MB
+        assert ex.value.status == P.ARA_E_BUDGET
+        assert P.ara_bytes_in_use(e.ctx) < (8 << 20)
+        h = P.ara_load_yet(e.ctx, np.zeros((16, 16), dtype=np.int32), 10)
+        assert h >= 0
