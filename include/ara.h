@@ -180,6 +180,55 @@ ara_status ara_risk_measures(ara_ctx *ctx, const float *ylt, int64_t n_trials,
 ara_status ara_set_profiling(ara_ctx *ctx, int32_t enabled);
 ara_status ara_last_kernel_ms(ara_ctx *ctx, double *ms_out);
 
+/*
+ * Sampling surrogate for the inverse-Beta step of section 3.3 (a fast method
+ * for the step the paper's timings show dominating; mode ARA_MODE_SURROGATE).
+ *
+ * Model: x = sigmoid(m + s v + NN(ln a / 2, ln b / 2, v / 3)) with v = Phi^-1(u),
+ * m = psi(a) - psi(b), s = sqrt(psi'(a) + psi'(b)) (the logit-normal
+ * approximation of the Beta quantile) and NN a 3 -> 64 -> 64 -> 1 perceptron
+ * with activation z sigmoid(1.702 z), BF16 weights, FP16 activations and FP32
+ * accumulation on the matrix cores.  Domain: a, b in [0.2, 50].  A table over
+ * 16 x 16 x 16 cells of (ln a, ln b, v) holds the largest absolute error in x
+ * seen on held-out points; draws outside the domain or in a cell whose bound
+ * exceeds the tolerance use the plain inverse.
+ *
+ * ara_surrogate_train: draws n_tuples training tuples on the device ((a, b)
+ * log-uniform on the domain; u on the 2^-24 grid, half uniform, half
+ * logit-uniform), labels them with the plain inverse, and runs `epochs` epochs
+ * of Adam (batch a multiple of 64, <= 65536; peak learning rate lr; warm-up
+ * then cosine decay) with the library's MFMA forward/backward kernels.
+ * Training continues from the current weights (fresh weights on the first
+ * call).  epoch_loss_out (optional, host, epochs doubles): mean squared error
+ * in x per epoch.
+ * ara_surrogate_calibrate: fills the error table from n_val fresh held-out
+ * tuples and marks cells whose largest error exceeds tol (or that saw no
+ * point) for fallback.  Outputs (optional, host): per-cell largest |error|
+ * and mean signed error (float [4096] each), number of marked cells.
+ * ara_surrogate_grad: loss and gradient (float [4481], host) of the mean
+ * squared error over n host tuples (f0, f1, f2, base, x; n a multiple of 64,
+ * <= 65536) at the current weights, without an update (gradient checks).
+ * ara_surrogate_tuples: n training tuples for seed (host float [n][5]).
+ * ara_surrogate_export / _import: FP32 weights (float [4481]), Adam moments
+ * (float [4481] each), step count and fallback mask (uint8 [4096]); any
+ * pointer may be NULL.  Import makes the surrogate ready.
+ * ara_surrogate_eval: x[i] for host (a, b, u) arrays, through the same
+ * surrogate-or-exact decision as the layer kernel; used_out[i] = 1 where the
+ * surrogate answered.
+ */
+ara_status ara_surrogate_train(ara_ctx *ctx, int64_t n_tuples, int32_t epochs, int32_t batch, double lr,
+                               uint32_t seed, double *epoch_loss_out);
+ara_status ara_surrogate_calibrate(ara_ctx *ctx, int64_t n_val, uint32_t seed, double tol,
+                                   float *cell_max_out, float *cell_bias_out, int32_t *n_marked_out);
+ara_status ara_surrogate_grad(ara_ctx *ctx, const float *tuples, int32_t n, float *grad_out, double *loss_out);
+ara_status ara_surrogate_tuples(ara_ctx *ctx, int64_t n, uint32_t seed, float *out);
+ara_status ara_surrogate_export(ara_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t *step,
+                                uint8_t *mask);
+ara_status ara_surrogate_import(ara_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
+                                int64_t step, const uint8_t *mask);
+ara_status ara_surrogate_eval(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
+                              double *x_out, int32_t *used_out);
+
 ara_status ara_philox_uniforms(ara_ctx *ctx, const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1,
                                float *out, void *hip_stream);
 ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,

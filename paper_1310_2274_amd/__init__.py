@@ -73,6 +73,13 @@ def lib() -> C.CDLL:
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
             "ara_set_profiling": (i32, [vp, i32]),
+            "ara_surrogate_train": (i32, [vp, i64, i32, i32, d, u32, vp]),
+            "ara_surrogate_calibrate": (i32, [vp, i64, u32, d, vp, vp, vp]),
+            "ara_surrogate_grad": (i32, [vp, vp, i32, vp, vp]),
+            "ara_surrogate_tuples": (i32, [vp, i64, u32, vp]),
+            "ara_surrogate_export": (i32, [vp, vp, vp, vp, vp, vp]),
+            "ara_surrogate_import": (i32, [vp, vp, vp, vp, i64, vp]),
+            "ara_surrogate_eval": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_last_kernel_ms": (i32, [vp, C.POINTER(C.c_double)]),
             "ara_beta_quantile": (i32, [vp, vp, vp, vp, i64, vp, vp]),
         }
@@ -242,6 +249,82 @@ def ara_last_kernel_ms(ctx) -> float:
     ms = C.c_double()
     _check(ctx, lib().ara_last_kernel_ms(ctx, C.byref(ms)))
     return ms.value
+
+
+SUR_PARAMS = 4481
+SUR_CELLS = 4096
+
+
+def ara_surrogate_train(ctx, n_tuples: int, epochs: int, batch: int = 4096, lr: float = 3e-3, seed: int = 1):
+    losses = np.zeros(max(1, epochs))
+    _check(ctx, lib().ara_surrogate_train(ctx, int(n_tuples), int(epochs), int(batch), float(lr),
+                                          int(seed) & 0xFFFFFFFF, losses.ctypes.data))
+    return losses[:epochs]
+
+
+def ara_surrogate_calibrate(ctx, n_val: int, seed: int = 2, tol: float = 1e-3):
+    cmax = np.zeros(SUR_CELLS, dtype=np.float32)
+    cbias = np.zeros(SUR_CELLS, dtype=np.float32)
+    nm = C.c_int32()
+    _check(ctx, lib().ara_surrogate_calibrate(ctx, int(n_val), int(seed) & 0xFFFFFFFF, float(tol),
+                                              cmax.ctypes.data, cbias.ctypes.data, C.byref(nm)))
+    return cmax, cbias, nm.value
+
+
+def ara_surrogate_grad(ctx, tuples):
+    t = np.ascontiguousarray(tuples, dtype=np.float32)
+    g = np.zeros(SUR_PARAMS, dtype=np.float32)
+    loss = C.c_double()
+    _check(ctx, lib().ara_surrogate_grad(ctx, t.ctypes.data, int(t.shape[0]), g.ctypes.data, C.byref(loss)))
+    return g, loss.value
+
+
+def ara_surrogate_tuples(ctx, n: int, seed: int):
+    out = np.zeros((int(n), 5), dtype=np.float32)
+    _check(ctx, lib().ara_surrogate_tuples(ctx, int(n), int(seed) & 0xFFFFFFFF, out.ctypes.data))
+    return out
+
+
+def ara_surrogate_export(ctx):
+    P = np.zeros(SUR_PARAMS, dtype=np.float32)
+    m = np.zeros(SUR_PARAMS, dtype=np.float32)
+    v = np.zeros(SUR_PARAMS, dtype=np.float32)
+    step = C.c_int64()
+    mask = np.zeros(SUR_CELLS, dtype=np.uint8)
+    _check(ctx, lib().ara_surrogate_export(ctx, P.ctypes.data, m.ctypes.data, v.ctypes.data, C.byref(step),
+                                           mask.ctypes.data))
+    return {"params": P, "adam_m": m, "adam_v": v, "step": step.value, "mask": mask}
+
+
+def ara_surrogate_import(ctx, params, adam_m=None, adam_v=None, step: int = 1, mask=None):
+    P = np.ascontiguousarray(params, dtype=np.float32)
+    m = None if adam_m is None else np.ascontiguousarray(adam_m, dtype=np.float32)
+    v = None if adam_v is None else np.ascontiguousarray(adam_v, dtype=np.float32)
+    k = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    _check(ctx, lib().ara_surrogate_import(ctx, P.ctypes.data, None if m is None else m.ctypes.data,
+                                           None if v is None else v.ctypes.data, int(step),
+                                           None if k is None else k.ctypes.data))
+
+
+def ara_surrogate_eval(ctx, a, b, u):
+    a, b, u = (np.ascontiguousarray(np.broadcast_to(t, np.broadcast(a, b, u).shape), dtype=np.float64)
+               for t in (np.asarray(a, np.float64), np.asarray(b, np.float64), np.asarray(u, np.float64)))
+    x = np.zeros(u.shape[0])
+    used = np.zeros(u.shape[0], dtype=np.int32)
+    _check(ctx, lib().ara_surrogate_eval(ctx, a.ctypes.data, b.ctypes.data, u.ctypes.data, int(u.shape[0]),
+                                         x.ctypes.data, used.ctypes.data))
+    return x, used
+
+
+def save_surrogate(ctx, path: str) -> None:
+    """Checkpoint the surrogate (weights, Adam state, fallback mask) as .npz."""
+    st = ara_surrogate_export(ctx)
+    np.savez(path, **{k: np.asarray(v) for k, v in st.items()})
+
+
+def load_surrogate(ctx, path: str) -> None:
+    with np.load(path, allow_pickle=False) as z:
+        ara_surrogate_import(ctx, z["params"], z["adam_m"], z["adam_v"], int(z["step"]), z["mask"])
 
 
 def ara_philox_uniforms(ctx, ctr, key0: int, key1: int, out=None, stream=None):

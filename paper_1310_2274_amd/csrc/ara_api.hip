@@ -15,6 +15,7 @@
 
 #include "../../include/ara.h"
 #include "ara_internal.hpp"
+#include "ara_surrogate.hpp"
 
 using namespace ara;
 
@@ -71,6 +72,12 @@ struct ara_ctx {
     hipEvent_t last = nullptr;
     hipStream_t last_stream = nullptr;
     bool have_last = false;
+    // sampling surrogate
+    bool sur_ready = false;
+    bool sur_init = false;
+    int64_t sur_step = 0;
+    DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_loss;
+    DevBuf sur_tuples, sur_gpart, sur_lpart, sur_calib;
     bool profiling = false;
     bool have_timing = false;
     hipEvent_t k_start = nullptr, k_stop = nullptr;
@@ -262,6 +269,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
     size_t b = align256((size_t)C * 16) + 2 * align256((size_t)C * 4) + align256(scan_scratch_words(C) * 4) +
                align256(p.total * sizeof(EntryRec));
     if (p.has_corr) b += align256(p.total * 8);
+    if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
     return b;
 }
 
@@ -298,6 +306,12 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     p.dev.rows = rows;
     p.dev.pent = pent;
     p.dev.pcw = pcw;
+    if (mode == ARA_MODE_SURROGATE) {
+        SurEntry* psur = (SurEntry*)q;
+        q += align256(p.total * sizeof(SurEntry));
+        HIPCHK(c, launch_sur_entries(pent, (int64_t)p.total, psur, s));
+        p.dev.psur = psur;
+    }
     return ARA_OK;
 }
 
@@ -308,7 +322,8 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     if (!c) return ARA_E_STATE;
     if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
         return fail(c, ARA_E_INVAL, "unknown mode %d", (int)mode);
-    if (mode == ARA_MODE_SURROGATE) return fail(c, ARA_E_INVAL, "surrogate mode needs a loaded surrogate");
+    if (mode == ARA_MODE_SURROGATE && !c->sur_ready)
+        return fail(c, ARA_E_STATE, "surrogate mode needs a trained or imported surrogate");
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live)
         return fail(c, ARA_E_STATE, "unknown YET handle %d", yh);
     if (n_layers < 1 || !layers || !ylt_outs) return fail(c, ARA_E_INVAL, "no layers or outputs");
@@ -384,8 +399,12 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl2))) return st;
     YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
     if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
-    HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, (const LayerDev*)layers_dev,
-                            n_layers, maxJ, seed, s));
+    if (mode == ARA_MODE_SURROGATE)
+        HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, seed,
+                                          (const MlpFrag*)c->sur_frag.p, (const uint32_t*)c->sur_mask.p, s));
+    else
+        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, (const LayerDev*)layers_dev,
+                                n_layers, maxJ, seed, s));
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(c->k_stop, s));
         c->have_timing = true;
@@ -408,6 +427,59 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     return ARA_OK;
 }
 
+
+// ---- surrogate state ----
+ara_status sur_alloc(ara_ctx* c)
+{
+    if (c->sur_init) return ARA_OK;
+    ara_status st;
+    const size_t pb = align256(kNumParams * 4);
+    if ((st = dev_alloc(c, c->sur_P, pb)) || (st = dev_alloc(c, c->sur_m, pb)) || (st = dev_alloc(c, c->sur_v, pb)) ||
+        (st = dev_alloc(c, c->sur_grad, pb)) || (st = dev_alloc(c, c->sur_frag, sizeof(MlpFrag))) ||
+        (st = dev_alloc(c, c->sur_mask, kCells / 8)) || (st = dev_alloc(c, c->sur_loss, 256)))
+        return st;
+    HIPCHK(c, hipMemset(c->sur_m.p, 0, pb));
+    HIPCHK(c, hipMemset(c->sur_v.p, 0, pb));
+    HIPCHK(c, hipMemset(c->sur_mask.p, 0, kCells / 8));
+    c->sur_step = 0;
+    c->sur_init = true;
+    return ARA_OK;
+}
+
+uint64_t splitmix(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+ara_status sur_tuples_dev(ara_ctx* c, int64_t n, uint32_t seed)
+{
+    ara_status st;
+    if ((st = ws_reserve(c, c->sur_tuples, (size_t)n * 20))) return st;
+    HIPCHK(c, sur_launch_tuplegen(n, seed, (float*)c->sur_tuples.p, nullptr));
+    return ARA_OK;
+}
+
+ara_status sur_step_ws(ara_ctx* c, int32_t batch)
+{
+    ara_status st;
+    const int nw = batch / 64;
+    if ((st = ws_reserve(c, c->sur_gpart, (size_t)nw * kNumParams * 4))) return st;
+    if ((st = ws_reserve(c, c->sur_lpart, (size_t)nw * 4 + 256))) return st;
+    return ARA_OK;
+}
 }  // namespace
 
 // ===========================================================================
@@ -469,6 +541,9 @@ void ara_destroy(ara_ctx* c)
     dev_free(c, c->ws_out);
     dev_free(c, c->ws_sel);
     dev_free(c, c->ws_in);
+    for (DevBuf* b : {&c->sur_P, &c->sur_m, &c->sur_v, &c->sur_grad, &c->sur_frag, &c->sur_mask, &c->sur_loss,
+                      &c->sur_tuples, &c->sur_gpart, &c->sur_lpart, &c->sur_calib})
+        dev_free(c, *b);
     for (auto& sl : c->stage) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.dev) (void)hipFree(sl.dev);
@@ -814,4 +889,196 @@ ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const
     return ARA_OK;
 }
 
+
+ara_status ara_surrogate_train(ara_ctx* c, int64_t n, int32_t epochs, int32_t batch, double lr, uint32_t seed,
+                               double* epoch_loss)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < batch || epochs < 0 || batch < 64 || batch % 64 || batch > 65536 || !(lr > 0.0) || n >= ((int64_t)1 << 31))
+        return fail(c, ARA_E_INVAL, "bad training arguments");
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    if ((st = sur_alloc(c))) return st;
+    if (c->sur_step == 0) HIPCHK(c, sur_launch_init((float*)c->sur_P.p, seed, nullptr));
+    if ((st = sur_tuples_dev(c, n, seed))) return st;
+    if ((st = sur_step_ws(c, batch))) return st;
+    const int64_t steps_per_epoch = n / batch;
+    const int64_t total = steps_per_epoch * (int64_t)epochs;
+    const int64_t warm = std::max<int64_t>(1, total / 10);
+    uint64_t rs = ((uint64_t)seed << 32) ^ 0xC0FFEEull;
+    int64_t t = 0;
+    for (int e = 0; e < epochs; ++e) {
+        uint64_t pa;
+        do {
+            pa = splitmix(rs) % (uint64_t)n;
+        } while (pa == 0 || gcd64(pa, (uint64_t)n) != 1);
+        const uint64_t pc = splitmix(rs) % (uint64_t)n;
+        HIPCHK(c, hipMemsetAsync(c->sur_loss.p, 0, 4, nullptr));
+        for (int64_t k = 0; k < steps_per_epoch; ++k, ++t) {
+            const double frac = (double)t / (double)std::max<int64_t>(1, total);
+            double f = 0.5 * (1.0 + std::cos(3.14159265358979 * frac));
+            if (t < warm) f *= (double)(t + 1) / (double)warm;
+            ++c->sur_step;
+            HIPCHK(c, sur_launch_train_step((const float*)c->sur_tuples.p, n, (int64_t)pa, (int64_t)pc, k * batch, batch,
+                                            (float*)c->sur_P.p, (float*)c->sur_m.p, (float*)c->sur_v.p,
+                                            (float*)c->sur_gpart.p, (float*)c->sur_lpart.p, (float*)c->sur_grad.p,
+                                            (float*)c->sur_loss.p, (float)(lr * f), c->sur_step, true, nullptr));
+        }
+        if (epoch_loss) {
+            float acc = 0.0f;
+            HIPCHK(c, hipMemcpy(&acc, c->sur_loss.p, 4, hipMemcpyDeviceToHost));
+            epoch_loss[e] = (double)acc / (double)(steps_per_epoch * batch);
+        }
+    }
+    HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->sur_ready = true;
+    return end_call(c, nullptr);
+}
+
+ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, double tol, float* cell_max,
+                                   float* cell_bias, int32_t* n_marked)
+{
+    if (!c) return ARA_E_STATE;
+    if (!c->sur_init) return fail(c, ARA_E_STATE, "no surrogate to calibrate");
+    if (n_val < 1 || !(tol > 0.0)) return fail(c, ARA_E_INVAL, "bad calibration arguments");
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    if ((st = sur_tuples_dev(c, n_val, seed))) return st;
+    const size_t cb = (size_t)kCells * (4 + 8 + 4);
+    if ((st = ws_reserve(c, c->sur_calib, cb))) return st;
+    unsigned int* cnt = (unsigned int*)c->sur_calib.p;
+    double* sum = (double*)((char*)c->sur_calib.p + kCells * 4);
+    unsigned int* mx = (unsigned int*)((char*)c->sur_calib.p + kCells * 12);
+    HIPCHK(c, hipMemset(c->sur_calib.p, 0, cb));
+    HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
+    HIPCHK(c, sur_launch_calib((const float*)c->sur_tuples.p, n_val, (const MlpFrag*)c->sur_frag.p, cnt, sum, mx,
+                               nullptr));
+    std::vector<unsigned int> hc(kCells), hm(kCells);
+    std::vector<double> hs(kCells);
+    HIPCHK(c, hipMemcpy(hc.data(), cnt, kCells * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(hs.data(), sum, kCells * 8, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(hm.data(), mx, kCells * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> bits(kCells / 32, 0u);
+    int marked = 0;
+    for (int i = 0; i < kCells; ++i) {
+        float m;
+        std::memcpy(&m, &hm[i], 4);
+        const bool bad = hc[i] == 0 || (double)m > tol;
+        if (bad) {
+            bits[i >> 5] |= 1u << (i & 31);
+            ++marked;
+        }
+        if (cell_max) cell_max[i] = hc[i] ? m : -1.0f;
+        if (cell_bias) cell_bias[i] = hc[i] ? (float)(hs[i] / hc[i]) : 0.0f;
+    }
+    HIPCHK(c, hipMemcpy(c->sur_mask.p, bits.data(), kCells / 8, hipMemcpyHostToDevice));
+    if (n_marked) *n_marked = marked;
+    c->sur_ready = true;
+    return end_call(c, nullptr);
+}
+
+ara_status ara_surrogate_grad(ara_ctx* c, const float* tuples, int32_t n, float* grad_out, double* loss_out)
+{
+    if (!c) return ARA_E_STATE;
+    if (!tuples || !grad_out || n < 64 || n % 64 || n > 65536) return fail(c, ARA_E_INVAL, "bad gradient arguments");
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    if ((st = sur_alloc(c))) return st;
+    if (c->sur_step == 0 && !c->sur_ready) HIPCHK(c, sur_launch_init((float*)c->sur_P.p, 1u, nullptr));
+    if ((st = ws_reserve(c, c->sur_tuples, (size_t)n * 20))) return st;
+    if ((st = sur_step_ws(c, n))) return st;
+    HIPCHK(c, hipMemcpy(c->sur_tuples.p, tuples, (size_t)n * 20, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemset(c->sur_loss.p, 0, 4));
+    HIPCHK(c, sur_launch_train_step((const float*)c->sur_tuples.p, n, 1, 0, 0, n, (float*)c->sur_P.p,
+                                    (float*)c->sur_m.p, (float*)c->sur_v.p, (float*)c->sur_gpart.p,
+                                    (float*)c->sur_lpart.p, (float*)c->sur_grad.p, (float*)c->sur_loss.p, 0.0f, 1,
+                                    false, nullptr));
+    HIPCHK(c, hipMemcpy(grad_out, c->sur_grad.p, kNumParams * 4, hipMemcpyDeviceToHost));
+    float acc = 0.0f;
+    HIPCHK(c, hipMemcpy(&acc, c->sur_loss.p, 4, hipMemcpyDeviceToHost));
+    if (loss_out) *loss_out = (double)acc / (double)n;
+    return end_call(c, nullptr);
+}
+
+ara_status ara_surrogate_tuples(ara_ctx* c, int64_t n, uint32_t seed, float* out)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 1 || !out) return fail(c, ARA_E_INVAL, "bad arguments to ara_surrogate_tuples");
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    if ((st = sur_tuples_dev(c, n, seed))) return st;
+    HIPCHK(c, hipMemcpy(out, c->sur_tuples.p, (size_t)n * 20, hipMemcpyDeviceToHost));
+    return end_call(c, nullptr);
+}
+
+ara_status ara_surrogate_export(ara_ctx* c, float* params, float* am, float* av, int64_t* step, uint8_t* mask)
+{
+    if (!c) return ARA_E_STATE;
+    if (!c->sur_init) return fail(c, ARA_E_STATE, "no surrogate to export");
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    HIPCHK(c, hipDeviceSynchronize());
+    if (params) HIPCHK(c, hipMemcpy(params, c->sur_P.p, kNumParams * 4, hipMemcpyDeviceToHost));
+    if (am) HIPCHK(c, hipMemcpy(am, c->sur_m.p, kNumParams * 4, hipMemcpyDeviceToHost));
+    if (av) HIPCHK(c, hipMemcpy(av, c->sur_v.p, kNumParams * 4, hipMemcpyDeviceToHost));
+    if (step) *step = c->sur_step;
+    if (mask) {
+        std::vector<uint32_t> bits(kCells / 32);
+        HIPCHK(c, hipMemcpy(bits.data(), c->sur_mask.p, kCells / 8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < kCells; ++i) mask[i] = (uint8_t)((bits[i >> 5] >> (i & 31)) & 1u);
+    }
+    return ARA_OK;
+}
+
+ara_status ara_surrogate_import(ara_ctx* c, const float* params, const float* am, const float* av, int64_t step,
+                                const uint8_t* mask)
+{
+    if (!c) return ARA_E_STATE;
+    if (!params) return fail(c, ARA_E_INVAL, "params is NULL");
+    for (int i = 0; i < kNumParams; ++i)
+        if (!std::isfinite(params[i])) return fail(c, ARA_E_INVAL, "non-finite parameter %d", i);
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    if ((st = sur_alloc(c))) return st;
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(c->sur_P.p, params, kNumParams * 4, hipMemcpyHostToDevice));
+    if (am) HIPCHK(c, hipMemcpy(c->sur_m.p, am, kNumParams * 4, hipMemcpyHostToDevice));
+    if (av) HIPCHK(c, hipMemcpy(c->sur_v.p, av, kNumParams * 4, hipMemcpyHostToDevice));
+    c->sur_step = step > 0 ? step : 1;
+    std::vector<uint32_t> bits(kCells / 32, 0u);
+    if (mask)
+        for (int i = 0; i < kCells; ++i)
+            if (mask[i]) bits[i >> 5] |= 1u << (i & 31);
+    HIPCHK(c, hipMemcpy(c->sur_mask.p, bits.data(), kCells / 8, hipMemcpyHostToDevice));
+    HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
+    HIPCHK(c, hipDeviceSynchronize());
+    c->sur_ready = true;
+    return end_call(c, nullptr);
+}
+
+ara_status ara_surrogate_eval(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n, double* x,
+                              int32_t* used)
+{
+    if (!c) return ARA_E_STATE;
+    if (!c->sur_ready) return fail(c, ARA_E_STATE, "no trained or imported surrogate");
+    if (n < 1 || !a || !b || !u || !x) return fail(c, ARA_E_INVAL, "bad arguments to ara_surrogate_eval");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(a[i] > 0.0) || !(b[i] > 0.0) || !(u[i] > 0.0 && u[i] < 1.0) || !std::isfinite(a[i]) || !std::isfinite(b[i]))
+            return fail(c, ARA_E_INVAL, "bad (a, b, u) at %lld", (long long)i);
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    const size_t nb = align256((size_t)n * 8);
+    if ((st = ws_reserve(c, c->ws_in, 4 * nb + align256((size_t)n * 4)))) return st;
+    char* q = (char*)c->ws_in.p;
+    HIPCHK(c, hipMemcpy(q, a, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(q + nb, b, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(q + 2 * nb, u, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, sur_launch_eval((const double*)q, (const double*)(q + nb), (const double*)(q + 2 * nb), n,
+                              (const MlpFrag*)c->sur_frag.p, (const uint32_t*)c->sur_mask.p, (double*)(q + 3 * nb),
+                              (int32_t*)(q + 4 * nb), nullptr));
+    HIPCHK(c, hipMemcpy(x, q + 3 * nb, (size_t)n * 8, hipMemcpyDeviceToHost));
+    if (used) HIPCHK(c, hipMemcpy(used, q + 4 * nb, (size_t)n * 4, hipMemcpyDeviceToHost));
+    return end_call(c, nullptr);
+}
 }  // extern "C"

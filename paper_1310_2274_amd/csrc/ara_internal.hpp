@@ -10,6 +10,9 @@ constexpr int kMaxEltsPerLayer = 64;
 constexpr int kMaxRp = 16;
 constexpr float kSigmaClamp = 0.999f;      // sigma_beta <= 0.999 * sigma_beta_max
 
+struct SurEntry;
+struct MlpFrag;
+
 // A loaded XELT as the kernels see it.
 struct EltDev {
     const int32_t* idx;     // [C] entry of each event, -1 if absent (direct-access table)
@@ -27,12 +30,13 @@ struct LayerDev {
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
+    const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
     float* ylt;             // [trial_end - trial_begin]
     float* omax;            // [trial_end - trial_begin] or null
     float occR, occL, aggR, aggL;
     uint32_t prog;
     int32_t J;
-    int32_t pad0, pad1;
+    int32_t pad0;
     float4 jt[kMaxEltsPerLayer];   // per-XELT (deductible, limit, share, 0)
 };
 
@@ -60,6 +64,12 @@ hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double oc
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
                          const LayerDev* layers, int32_t n_layers, int32_t max_J, uint32_t seed,
                          hipStream_t s);
+
+// ---- surrogate (ara_surrogate.hip) ----
+hipError_t launch_sur_entries(const EntryRec* pent, int64_t n, SurEntry* psur, hipStream_t s);
+hipError_t launch_layers_surrogate(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
+                                   int32_t n_layers, uint32_t seed, const MlpFrag* frag, const uint32_t* cellmask,
+                                   hipStream_t s);
 
 hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s);
 hipError_t launch_beta_quantile(const double* a, const double* b, const double* u, int64_t n, double* x, hipStream_t s);

@@ -14,65 +14,9 @@
 //     per-lane sum combined across lanes with TwoSum in a fixed butterfly, so
 //     every YLT value is a deterministic function of its trial.
 #include "ara_internal.hpp"
+#include "ara_wave.hpp"
 
 namespace ara {
-
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// inclusive prefix sum over the 64 lanes of a wave
-__device__ __forceinline__ int wave_incl_scan(int v)
-{
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int o = __shfl_up(v, d, 64);
-        if (lane >= d) v += o;
-    }
-    return v;
-}
-
-// (hi, lo) compensated pair: error-free sum of the high parts, low parts added
-__device__ __forceinline__ void two_sum_merge(float& hi, float& lo, float ohi, float olo)
-{
-    const float s = hi + ohi;
-    const float bb = s - hi;
-    const float err = (hi - (s - bb)) + (ohi - bb);
-    hi = s;
-    lo = (lo + olo) + err;
-}
-
-__device__ __forceinline__ void neumaier_add(float& s, float& c, float x)
-{
-    const float t = s + x;
-    if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
-    else c += (x - t) + s;
-    s = t;
-}
-
-// Sum of (hi, lo) over the wave; every lane ends with the same pair.
-__device__ __forceinline__ void wave_sum_pair(float& hi, float& lo)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const float oh = __shfl_xor(hi, m, 64);
-        const float ol = __shfl_xor(lo, m, 64);
-        two_sum_merge(hi, lo, oh, ol);
-    }
-}
-
-__device__ __forceinline__ float wave_max(float v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, 64));
-    return v;
-}
 
 // ===========================================================================
 // Load-time kernels
@@ -252,32 +196,6 @@ constexpr int kWavesPerBlock = 4;
 constexpr int kChunk = 64;                   // event slots per compaction round
 constexpr int kRound = 16;                   // draws per slot per drain round
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
-
-__device__ __forceinline__ void trial_range(const YetDev& y, int64_t i, int64_t& row, int32_t& len)
-{
-    if (y.offs) {
-        row = y.offs[i];
-        len = (int32_t)(y.offs[i + 1] - row);
-    } else {
-        row = i * (int64_t)y.K;
-        len = y.K;
-    }
-}
-
-// Draw z for one (trial, slot, XELT) hit: section 3.1 uniforms, section 3.2
-// combination when the entry has a correlated part.
-template <bool HAS_CORR>
-__device__ __forceinline__ double draw_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed, uint32_t prog,
-                                         const float2* pcw, uint32_t pi)
-{
-    const double ui = (double)u01(philox_word0(trial, slot, j, 0u, seed, prog));
-    if (!HAS_CORR || !pcw) return ui;
-    const float2 w = pcw[pi];
-    if (w.y == 0.0f) return ui;
-    const double uc = (double)u01(philox_word0(trial, slot, 0xFFFFFFFFu, 1u, seed, 0xFFFFFFFFu));
-    if (w.x == 0.0f) return uc;
-    return normcdf((double)w.x * normcdfinv(ui) + (double)w.y * normcdfinv(uc));
-}
 
 template <bool HAS_CORR>
 __global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,

@@ -24,9 +24,11 @@ Recipe (master seed 1310, numpy PCG64 sub-streams derived per table):
 * Layer terms are sized from E = K * sum(n_j) / C, the expected number of
   (event, ELT) hits per trial, so that every clamp binds on a fraction of
   trials (values per workload below).  At paper scale the trial's cumulative
-  occurrence loss S lies in about [1.07, 1.31] * E * L0, so the aggregate
-  retention 1.12 * E * L0 (about its 10% quantile) and limit 0.08 * E * L0
-  both bind.
+  occurrence loss S lies in about [1.07, 1.31] * E * L0 (oracle, 4,000
+  trials: 10% quantile 1.126, 99.9% quantile 1.289), so the aggregate
+  retention 1.12 * E * L0 zeroes about 8% of trials and the limit
+  0.17 * E * L0 caps about 0.1% -- beyond the 250-year return period, so the
+  PML/TVaR at 10-250 years are not all pinned to the limit.
 """
 from __future__ import annotations
 
@@ -171,7 +173,7 @@ def paper_scale(n_trials: int = 800_000, seed: int = MASTER_SEED) -> Workload:
     elts = _elts(rng, C, 16, 20_000, 50_000)
     E = K * sum(e.n for e in elts) / C
     lay = Layer(elts, occ_retention=L0, occ_limit=20 * L0,
-                agg_retention=1.12 * E * L0, agg_limit=0.08 * E * L0)
+                agg_retention=1.12 * E * L0, agg_limit=0.17 * E * L0)
     return Workload(f"paper_{n_trials}x1000_16elt", n_trials, K, C, [lay], seed=seed, yet_seed=seed)
 
 

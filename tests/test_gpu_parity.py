@@ -171,8 +171,9 @@ def test_paper_scale_sampled_trials(eng):
     yo, g, _ = oracle_ylt(wl, trials, oracle.MODE_PLAIN, wl.seed, threads=0)
     worst = assert_ylt_close(y[trials], yo, g, "paper scale")
     print(f"paper scale: worst |dY|/G = {worst:.3e} over {trials.size} trials")
-    # the aggregate clamps bind at this scale
-    assert 0.01 < np.mean(y == 0) < 0.99 and 0.01 < np.mean(y == np.float32(wl.layers[0].agg_limit)) < 0.99
+    # both aggregate clamps bind at this scale (retention often, limit rarely)
+    assert 0.01 < np.mean(y == 0) < 0.5
+    assert 0 < np.sum(y == np.float32(wl.layers[0].agg_limit)) < 0.004 * y.size
     # risk measures of the GPU YLT: exact order statistic, FP64 tail mean
     rps = [10, 50, 100, 250]
     pml, tvar = P.ara_risk_measures(eng.ctx, torch.from_numpy(y.astype(np.float32)).cuda(), rps)

@@ -1,0 +1,103 @@
+"""GPU tests of the sampling surrogate: MFMA gradients against the FP64
+reference, labels of the training tuples, trained error bounds with fallback,
+checkpointing, and the surrogate layer kernel against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import oracle
+from oracle import mlp_ref
+import paper_1310_2274_amd as P
+from paper_1310_2274_amd import synth
+from gpu_helpers import gpu_ylt, oracle_ylt, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def eng():
+    torch_cuda()
+    e = P.Engine(0)
+    yield e
+    e.close()
+
+
+def test_training_tuples_features_and_labels(eng):
+    T = P.ara_surrogate_tuples(eng.ctx, 4096, seed=5).astype(np.float64)
+    a, b, v = np.exp(2 * T[:, 0]), np.exp(2 * T[:, 1]), 3 * T[:, 2]
+    assert np.all((a > 0.199) & (a < 50.1) & (b > 0.199) & (b < 50.1))
+    base = sp.digamma(a) - sp.digamma(b) + np.sqrt(sp.polygamma(1, a) + sp.polygamma(1, b)) * v
+    assert np.allclose(T[:, 3], base, rtol=1e-4, atol=1e-4)
+    u = sp.ndtr(v)
+    x = oracle.beta_inc_inv_vec(u, a, b)
+    # a, b, u are recovered from FP32 features, so the label matches to the conditioning of that rounding
+    assert np.median(np.abs(T[:, 4] - x)) < 1e-5 and np.quantile(np.abs(T[:, 4] - x), 0.99) < 1e-3
+
+
+def test_mfma_gradient_matches_fp64_reference(eng):
+    T = P.ara_surrogate_tuples(eng.ctx, 1024, seed=7)
+    # fresh weights: import a known random parameter vector
+    rng = np.random.default_rng(3)
+    Pw = np.concatenate([rng.uniform(-0.3, 0.3, 192), np.zeros(64), rng.uniform(-0.2, 0.2, 4096), np.zeros(64),
+                         rng.uniform(-0.05, 0.05, 64), [0.0]]).astype(np.float32)
+    P.ara_surrogate_import(eng.ctx, Pw)
+    g, loss = P.ara_surrogate_grad(eng.ctx, T)
+    Pq = mlp_ref.round_bf16(Pw)
+    Tq = T.astype(np.float64)
+    Tq[:, :3] = T[:, :3].astype(np.float16).astype(np.float64)
+    gr, lr = mlp_ref.grad(Pq, Tq)
+    assert loss == pytest.approx(lr, rel=2e-3)
+    for name, lo, hi in [("W1", 0, 192), ("b1", 192, 256), ("W2", 256, 4352), ("b2", 4352, 4416),
+                         ("w3", 4416, 4480), ("b3", 4480, 4481)]:
+        d, r = g[lo:hi].astype(np.float64), gr[lo:hi]
+        rel = np.linalg.norm(d - r) / max(np.linalg.norm(r), 1e-30)
+        assert rel < 2e-2, (name, rel)
+
+
+def test_train_calibrate_and_error_bounds(eng, tmp_path):
+    losses = P.ara_surrogate_train(eng.ctx, 1_048_576, epochs=4, batch=4096, lr=3e-3, seed=11)
+    assert losses[-1] < losses[0] and np.isfinite(losses).all()
+    cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
+    assert 0 <= marked < P.SUR_CELLS
+    # fresh held-out points: where the table allows the surrogate, its error respects the bound
+    rng = np.random.default_rng(9)
+    n = 20000
+    a = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
+    b = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
+    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    x, used = P.ara_surrogate_eval(eng.ctx, a, b, u)
+    xo = oracle.beta_inc_inv_vec(u, a, b)
+    err = np.abs(x - xo)
+    assert np.all(err[used == 0] <= 1e-8 + 1e-8 * xo[used == 0])          # fallback is the plain inverse
+    if used.any():
+        # an empirical bound: allow a sliver of fresh points past it, none far past it
+        assert np.mean(err[used == 1] > 1e-3) < 2e-3
+        assert err[used == 1].max() < 5e-3
+    # outside the domain the plain inverse always answers
+    x2, used2 = P.ara_surrogate_eval(eng.ctx, np.array([0.1, 60.0]), np.array([1.0, 2.0]), np.array([0.3, 0.3]))
+    assert list(used2) == [0, 0]
+    # checkpoint round trip reproduces the same answers
+    path = str(tmp_path / "sur.npz")
+    P.save_surrogate(eng.ctx, path)
+    with P.Engine(0) as e2:
+        P.load_surrogate(e2.ctx, path)
+        x3, used3 = P.ara_surrogate_eval(e2.ctx, a[:512], b[:512], u[:512])
+    assert np.array_equal(x3, x[:512]) and np.array_equal(used3, used[:512])
+    print(f"surrogate: final loss {losses[-1]:.3e}, marked cells {marked}/{P.SUR_CELLS}, "
+          f"surrogate share {used.mean():.3f}, max err {err[used == 1].max() if used.any() else 0:.2e}")
+
+
+def test_surrogate_layer_close_to_oracle(eng):
+    # after the training test: the surrogate layer stays within the surrogate's
+    # per-draw bound of the oracle, and matches the plain layer where it falls back
+    wl = synth.custom(256, 200, 3000, 6, 400, 1200, seed=19)
+    y, _ = gpu_ylt(eng, wl, P.MODE_SURROGATE, 4)
+    yo, g, _ = oracle_ylt(wl, np.arange(wl.n_trials), oracle.MODE_PLAIN, 4)
+    # every draw's loss error is at most 5e-3 * max_l <= 5e-3 * 10 * mean: bound by the gross loss
+    assert np.all(np.abs(y - yo) <= 0.05 * g + 1e-3)
+    assert np.mean(np.abs(y - yo)) <= 2e-3 * np.mean(g)
+    # deterministic
+    y2, _ = gpu_ylt(eng, wl, P.MODE_SURROGATE, 4)
+    assert np.array_equal(y, y2)

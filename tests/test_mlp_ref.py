@@ -1,0 +1,36 @@
+"""Pin of the FP64 surrogate reference: its analytic gradient against central
+finite differences of its own loss (a plainly different computation)."""
+import numpy as np
+
+from oracle import mlp_ref
+
+
+def test_reference_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    P = rng.normal(0, 0.3, mlp_ref.N_PARAMS)
+    T = np.column_stack([rng.normal(0, 1, (128, 3)), rng.normal(0, 1, 128), rng.uniform(0, 1, 128)])
+    g, loss = mlp_ref.grad(P, T)
+    assert np.isclose(loss, mlp_ref.forward(P, T)[1])
+    idx = np.concatenate([rng.choice(192, 6, replace=False), 192 + rng.choice(64, 4, replace=False),
+                          256 + rng.choice(4096, 10, replace=False), 4352 + rng.choice(64, 4, replace=False),
+                          4416 + rng.choice(64, 4, replace=False), [4480]])
+    h = 1e-6
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        fd = (mlp_ref.forward(Pp, T)[1] - mlp_ref.forward(Pm, T)[1]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(fd)) + 1e-10, (i, fd, g[i])
+
+
+def test_activation_and_bf16_rounding():
+    z = np.linspace(-6, 6, 101)
+    assert np.allclose(mlp_ref.g(z), z / (1 + np.exp(-1.702 * z)))
+    h = 1e-6
+    assert np.allclose(mlp_ref.g_prime(z), (mlp_ref.g(z + h) - mlp_ref.g(z - h)) / (2 * h), atol=1e-8)
+    # BF16 keeps 7 explicit significand bits: 1 + 2^-7 is representable,
+    # 1 + 2^-8 is a tie that rounds to even (1), 1 + 3 * 2^-8 rounds up
+    x = np.array([1.0, 1.0078125, 1.00390625, 1.01171875, -3.14159, 0.0])
+    r = mlp_ref.round_bf16(x)
+    assert list(r[[0, 1, 2, 3, 5]]) == [1.0, 1.0078125, 1.0, 1.015625, 0.0]
+    assert abs(r[4] - x[4]) <= 2 ** -8 * abs(x[4])
