@@ -8,9 +8,11 @@ XELT / occurrence / aggregate terms, write the YLT) followed by
 ara_risk_measures (PML and TVaR at 10/50/100/250 years).  Inputs are
 resident in HBM before timing starts.
 
-Printed: one JSON line with the metric (trial-events/s), the roofline of the
-dominant kernel, the streaming-phase (mean mode) roofline and the FP64 oracle
-timed on this host on a bounded sample of the same workload.
+Printed: one JSON line with the metric (trial-events/s of the plain form),
+the roofline of the dominant kernel, the streaming-phase (mean mode)
+roofline, the surrogate form (speed and PML/TVaR difference), optional
+portfolio-batch and serving legs, and the FP64 oracle timed on this host on
+a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -30,23 +32,24 @@ PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
 # (one FP32 or FP64 FMA per lane per clock without packed math).
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# Per-draw VALU lane-operations of the plain layer kernel, from rocprofv3
-# SQ_INSTS_VALU x 64 / draws on this workload (profiles/, design notes);
-# None until measured for the current kernel.
-VALU_OPS_PER_DRAW = None
-# HBM traffic per launch of the plain layer kernel from FETCH_SIZE/WRITE_SIZE
-# counters, scaled by a copy-kernel calibration; None when not measured for
-# the current kernel.
-TRAFFIC_BYTES = None
+# VALU lane-operations per draw of the plain layer kernel on this workload,
+# SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
+VALU_OPS_PER_DRAW = 3215.0
+# HBM bytes per launch of the plain layer kernel at 800,000 trials: FETCH_SIZE
+# (x2, copy-kernel calibration) + WRITE_SIZE, measured on the 100,000-trial
+# slice and scaled by 8 (profiles/k_layer_plain_paper100k_counters.md).
+TRAFFIC_BYTES = 8 * (2 * 12787253.8 + 1188.5) * 1024
 
 
-def count_draws(wl) -> int:
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def count_draws(yet, layer, catalog_size) -> int:
     """Number of (trial, slot, XELT) hits: the draws one pass makes."""
-    lay = wl.layers[0]
-    cnt = np.zeros(wl.catalog_size, dtype=np.int64)
-    for e in lay.elts:
+    cnt = np.zeros(catalog_size, dtype=np.int64)
+    for e in layer.elts:
         cnt[e.event_id] += 1
-    yet = wl.yet()
     total = 0
     for lo in range(0, yet.shape[0], 65536):
         total += int(cnt[yet[lo:lo + 65536]].sum())
@@ -72,14 +75,118 @@ def cpu_baseline(wl, seconds: float, threads: int):
                       f"trial-events, {t_used:.1f} s, FP64 C oracle, OpenMP over trials)"}
 
 
+def timed_steps(P, torch, eng, yh, desc, mode, seed, out, rps, steps, warmup):
+    for _ in range(warmup):
+        P.ara_run_layer(eng.ctx, yh, desc, mode, seed, out)
+        P.ara_risk_measures(eng.ctx, out, rps)
+    torch.cuda.synchronize()
+    P.ara_set_profiling(eng.ctx, True)
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.ara_run_layer(eng.ctx, yh, desc, mode, seed, out)
+        pml, tvar = P.ara_risk_measures(eng.ctx, out, rps)
+        kms.append(P.ara_last_kernel_ms(eng.ctx))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P.ara_set_profiling(eng.ctx, False)
+    return dt / steps, float(np.mean(kms)), pml, tvar
+
+
+def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s, plain_pml, plain_tvar,
+                  n_tuples, epochs, ckpt):
+    t0 = time.perf_counter()
+    losses = P.ara_surrogate_train(eng.ctx, n_tuples, epochs=epochs, batch=4096, lr=3e-3, seed=11)
+    t_train = time.perf_counter() - t0
+    cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 4_000_000, seed=12, tol=1e-3)
+    log(f"surrogate trained in {t_train:.1f} s (loss {losses[0]:.2e} -> {losses[-1]:.2e}), "
+        f"{marked}/{P.SUR_CELLS} cells fall back")
+    if ckpt:
+        P.save_surrogate(eng.ctx, ckpt)
+    step_s, kms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_SURROGATE, wl.seed, out, rps, steps, warmup)
+    rel_p = np.abs(pml - plain_pml) / np.abs(plain_pml)
+    rel_t = np.abs(tvar - plain_tvar) / np.abs(plain_tvar)
+    return {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
+            "speedup_vs_plain": plain_step_s / step_s, "pml": pml.tolist(), "tvar": tvar.tolist(),
+            "pml_rel_diff_vs_plain": rel_p.tolist(), "tvar_rel_diff_vs_plain": rel_t.tolist(),
+            "train": {"tuples": n_tuples, "epochs": epochs, "seconds": t_train, "final_mse": float(losses[-1])},
+            "fallback_cells": int(marked), "cells": P.SUR_CELLS,
+            "note": "PML/TVaR differences are against the plain GPU path, which matches the FP64 oracle per "
+                    "trial far inside 1e-5 of the gross loss (tests/test_gpu_parity.py)"}
+
+
+def portfolio_leg(P, torch, synth, steps):
+    wl = synth.portfolio()
+    eng = P.Engine(0)
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
+    outs = [torch.empty(wl.n_trials, device="cuda") for _ in descs]
+    res = {}
+    for name, mode in (("plain", P.MODE_PLAIN), ("surrogate", P.MODE_SURROGATE)):
+        if mode == P.MODE_SURROGATE:
+            P.ara_surrogate_train(eng.ctx, 4_000_000, epochs=10, batch=4096, lr=3e-3, seed=11)
+            P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
+        P.ara_run_layers(eng.ctx, yh, descs, mode, wl.seed, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P.ara_run_layers(eng.ctx, yh, descs, mode, wl.seed, outs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms_per_step": dt * 1e3,
+                     "trial_events_per_s": len(descs) * wl.trial_events / dt}
+        log(f"portfolio {name}: {dt * 1e3:.1f} ms for {len(descs)} layers")
+    eng.close()
+    res["workload"] = f"{wl.n_trials} trials x {wl.events_per_trial} events, {len(wl.layers)} layers " \
+                      f"({sum(len(l.elts) for l in wl.layers)} XELTs), one launch per step"
+    return res
+
+
+def serving_leg(P, torch, synth, rate, n_warm, n_meas, mode_name):
+    from paper_1310_2274_amd import serving
+    wl = synth.serving_yet()
+    eng = P.Engine(0)
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    mode = P.MODE_SURROGATE if mode_name == "surrogate" else P.MODE_PLAIN
+    if mode == P.MODE_SURROGATE:
+        P.ara_surrogate_train(eng.ctx, 4_000_000, epochs=10, batch=4096, lr=3e-3, seed=11)
+        P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
+    n = n_warm + n_meas
+    arr = serving.poisson_arrivals(rate, n, seed=4)
+    reqs = [serving.Request(i, synth.pricing_request(i), seed=1000 + i, arrival=float(arr[i])) for i in range(n)]
+    srv = serving.PricingServer(eng, yh, wl.n_trials, wl.events_per_trial, wl.catalog_size, mode,
+                                hbm_budget_bytes=64 << 30, tile=65536)
+    t0 = time.perf_counter()
+    done = srv.run_open_loop(reqs)
+    wall = time.perf_counter() - t0
+    meas = [r for r in done if r.req_id >= n_warm]
+    st = serving.latency_stats(meas)
+    eng.close()
+    st.update({"rate_req_per_s": rate, "mode": mode_name, "requests": n_meas, "warmup_requests": n_warm,
+               "trial_events_per_s": len(done) * wl.trial_events / wall, "wall_s": wall, "ticks": srv.ticks,
+               "budget_refusals": srv.refusals,
+               "workload": f"resident YET {wl.n_trials} x {wl.events_per_trial}, catalog {wl.catalog_size}; "
+                           f"requests of log-uniform 1-32 XELTs x 10k-60k entries"})
+    log(f"serving {mode_name} @ {rate}/s: p50 {st['p50_s'] * 1e3:.0f} ms, p99 {st['p99_s'] * 1e3:.0f} ms")
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--trials", type=int, default=800_000)
-    ap.add_argument("--mode", choices=["plain", "mean"], default="plain")
-    ap.add_argument("--no-mean-leg", action="store_true", help="skip the streaming-phase (mean mode) roofline leg")
+    ap.add_argument("--no-mean-leg", action="store_true", help="skip the streaming-phase (mean mode) leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--sur-tuples", type=int, default=10_000_000)
+    ap.add_argument("--sur-epochs", type=int, default=20)
+    ap.add_argument("--sur-ckpt", default="")
+    ap.add_argument("--portfolio", action="store_true", help="add the 64-layer portfolio-batch leg")
+    ap.add_argument("--serve", default="", help="serving leg: comma-separated request rates, e.g. 5,20")
+    ap.add_argument("--serve-mode", default="plain", choices=["plain", "surrogate"])
+    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget (0 = skip)")
     args = ap.parse_args()
 
@@ -98,91 +205,68 @@ def main():
     wl = synth.paper_scale(n_trials=args.trials)
     lay = wl.layers[0]
     N, K = wl.n_trials, wl.events_per_trial
-    print(f"[bench] generating {N}x{K} YET", file=sys.stderr, flush=True)
+    log(f"generating {N}x{K} YET")
     yet = wl.yet()
-    draws = count_draws(wl)
+    draws = count_draws(yet, lay, wl.catalog_size)
     eng = P.Engine(0)
     yh = eng.load_yet(yet, wl.catalog_size)
     desc = eng.load_layer(lay, wl.catalog_size)
     out = torch.empty(N, dtype=torch.float32, device="cuda")
     rps = P.DEFAULT_RETURN_PERIODS
-    mode = P.MODE_PLAIN if args.mode == "plain" else P.MODE_MEAN
-    print(f"[bench] setup {time.perf_counter() - t_setup:.1f} s, {draws} draws/pass", file=sys.stderr, flush=True)
+    log(f"setup {time.perf_counter() - t_setup:.1f} s, {draws} draws/pass")
 
-    def step(m):
-        P.ara_run_layer(eng.ctx, yh, desc, m, wl.seed, out)
-        return P.ara_risk_measures(eng.ctx, out, rps)
-
-    for _ in range(args.warmup):
-        step(mode)
-    torch.cuda.synchronize()
-    P.ara_set_profiling(eng.ctx, True)
-    kms = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pml, tvar = step(mode)
-        kms.append(P.ara_last_kernel_ms(eng.ctx))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    value = N * K * args.steps / dt
-    kernel_ms = float(np.mean(kms))
-    print(f"[bench] {args.mode}: {ms_per_step:.2f} ms/step, layer kernel {kernel_ms:.2f} ms", file=sys.stderr,
-          flush=True)
-
-    if mode == P.MODE_PLAIN:
-        if VALU_OPS_PER_DRAW is not None:
-            ach = VALU_OPS_PER_DRAW * draws / (kernel_ms * 1e-3) / 1e12
-            roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
-                    "traffic": TRAFFIC_BYTES}
-        else:
-            roof = {"bound": "alu", "achieved": None, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": None,
-                    "traffic": None}
-        roof.update({"kernel": "k_layer_plain", "kernel_ms": kernel_ms, "draws_per_launch": draws,
-                     "draws_per_s": draws / (kernel_ms * 1e-3)})
-    else:
-        gbs = (N * K * 4 + N * 4) / (kernel_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                "traffic": None, "kernel": "k_layer_mean", "kernel_ms": kernel_ms}
+    step_s, kernel_ms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps,
+                                               args.steps, args.warmup)
+    value = N * K / step_s
+    log(f"plain: {step_s * 1e3:.2f} ms/step, layer kernel {kernel_ms:.2f} ms")
+    ach = VALU_OPS_PER_DRAW * draws / (kernel_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
+            "traffic": TRAFFIC_BYTES if N == 800_000 else None, "kernel": "k_layer_plain", "kernel_ms": kernel_ms,
+            "draws_per_launch": draws, "draws_per_s": draws / (kernel_ms * 1e-3),
+            "ops_per_draw": VALU_OPS_PER_DRAW}
 
     mean_leg = None
-    if mode == P.MODE_PLAIN and not args.no_mean_leg:
-        for _ in range(2):
-            step(P.MODE_MEAN)
-        mk = []
-        tm0 = time.perf_counter()
-        for _ in range(max(3, args.steps)):
-            step(P.MODE_MEAN)
-            mk.append(P.ara_last_kernel_ms(eng.ctx))
-        tmd = (time.perf_counter() - tm0) / max(3, args.steps)
-        mkm = float(np.mean(mk))
-        gbs = (N * K * 4 + N * 4) / (mkm * 1e-3) / 1e9
-        mean_leg = {"bound": "hbm", "kernel": "k_layer_mean", "kernel_ms": mkm, "achieved": gbs,
+    if not args.no_mean_leg:
+        mstep, mk, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_MEAN, wl.seed, out, rps, max(3, args.steps), 2)
+        gbs = (N * K * 4 + N * 4) / (mk * 1e-3) / 1e9
+        mean_leg = {"bound": "hbm", "kernel": "k_layer_mean", "kernel_ms": mk, "achieved": gbs,
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "algorithmic_bytes": N * K * 4 + N * 4, "ms_per_step": tmd * 1e3,
-                    "trial_events_per_s": N * K / tmd}
-        print(f"[bench] mean mode: kernel {mkm:.3f} ms = {gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    P.ara_set_profiling(eng.ctx, False)
+                    "algorithmic_bytes": N * K * 4 + N * 4, "ms_per_step": mstep * 1e3,
+                    "trial_events_per_s": N * K / mstep}
+        log(f"mean mode: kernel {mk:.3f} ms = {gbs:.0f} GB/s")
+
+    sur = None
+    if not args.no_surrogate:
+        sur = surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar,
+                            args.sur_tuples, args.sur_epochs, args.sur_ckpt)
+        log(f"surrogate: {sur['ms_per_step']:.2f} ms/step, x{sur['speedup_vs_plain']:.2f} vs plain, "
+            f"max PML/TVaR rel diff {max(sur['pml_rel_diff_vs_plain'] + sur['tvar_rel_diff_vs_plain']):.2e}")
     eng.close()
+
+    port = portfolio_leg(P, torch, synth, max(1, args.steps // 2)) if args.portfolio else None
+    serve = None
+    if args.serve:
+        serve = [serving_leg(P, torch, synth, float(r), args.serve_warmup, args.serve_requests, args.serve_mode)
+                 for r in args.serve.split(",")]
 
     cpu = None
     if args.cpu_seconds > 0:
         threads = len(os.sched_getaffinity(0))
-        print(f"[bench] CPU oracle baseline on {threads} threads", file=sys.stderr, flush=True)
+        log(f"CPU oracle baseline on {threads} threads")
         cpu = cpu_baseline(wl, args.cpu_seconds, threads)
 
     rec = {
         "metric": "trial-events/s", "value": value, "unit": "trial-events/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mode == P.MODE_PLAIN else "f32",
-        "data": "synthetic",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"{N} trials x {K} events/trial, 100,000-event catalog, 1 layer of 16 XELTs "
-                               f"(20k-50k entries), {args.mode} sampling, PML/TVaR at 10/50/100/250 yr",
-                   "n_trials": N, "events_per_trial": K, "n_elts": len(lay.elts), "mode": args.mode,
-                   "draws_per_step": draws},
+                               f"(20k-50k entries), plain inverse-Beta sampling, PML/TVaR at 10/50/100/250 yr",
+                   "n_trials": N, "events_per_trial": K, "n_elts": len(lay.elts), "draws_per_step": draws},
         "roofline": roof,
         "roofline_streaming": mean_leg,
+        "surrogate": sur,
+        "portfolio": port,
+        "serving": serve,
         "cpu_baseline": cpu,
         "pml": [float(v) for v in pml], "tvar": [float(v) for v in tvar],
         "context": {"paper_c2075_trial_events_per_s": 8e8 / 41.0,

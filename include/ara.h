@@ -146,6 +146,21 @@ ara_status ara_run_layers(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc
                           float *const *ylt_outs, void *hip_stream);
 
 /*
+ * Prepared layers: the layer tables of `layer` for `mode` are built once and
+ * kept (they no longer refer to the XELTs, which may be freed).
+ * ara_run_prepared evaluates n prepared layers (all of one mode) over trials
+ * [trial_begin, trial_end) in one launch, each with its own seed, writing
+ * ylt_outs[l][i - trial_begin] (device pointers) and, where max_occ_outs is not
+ * NULL and its entry not NULL, the largest occurrence loss per trial.
+ * Results are those of ara_run_layer_ex for each layer alone.
+ */
+ara_status ara_prepare_layer(ara_ctx *ctx, const ara_layer_desc *layer, ara_mode mode, int32_t *layer_handle);
+ara_status ara_free_layer(ara_ctx *ctx, int32_t layer_handle);
+ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *layer_handles, int32_t n_layers,
+                            const uint32_t *seeds, int64_t trial_begin, int64_t trial_end,
+                            float *const *ylt_outs, float *const *max_occ_outs, void *hip_stream);
+
+/*
  * PML and TVaR (section 2.4) of a YLT of n_trials floats (device or host):
  * for each return period RP, k = floor(n_trials / RP) (ARA_E_RANGE if k < 1);
  * PML = the k-th largest year loss; TVaR = the mean of the k largest, summed in

@@ -73,6 +73,10 @@ def lib() -> C.CDLL:
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
             "ara_set_profiling": (i32, [vp, i32]),
+            "ara_prepare_layer": (i32, [vp, C.POINTER(LayerDesc), C.c_int, C.POINTER(i32)]),
+            "ara_free_layer": (i32, [vp, i32]),
+            "ara_run_prepared": (i32, [vp, i32, C.POINTER(i32), i32, C.POINTER(u32), i64, i64, C.POINTER(vp),
+                                       C.POINTER(vp), vp]),
             "ara_surrogate_train": (i32, [vp, i64, i32, i32, d, u32, vp]),
             "ara_surrogate_calibrate": (i32, [vp, i64, u32, d, vp, vp, vp]),
             "ara_surrogate_grad": (i32, [vp, vp, i32, vp, vp]),
@@ -226,6 +230,30 @@ def ara_run_layers(ctx, yet_handle: int, layers: Sequence[LayerDesc], mode: int,
     outs = (C.c_void_p * n)(*[_ptr(o) for o in ylt_outs])
     _check(ctx, lib().ara_run_layers(ctx, int(yet_handle), arr, n, int(mode), int(seed) & 0xFFFFFFFF, outs,
                                      _stream(stream, *ylt_outs)))
+
+
+def ara_prepare_layer(ctx, layer: LayerDesc, mode: int) -> int:
+    h = C.c_int32()
+    _check(ctx, lib().ara_prepare_layer(ctx, C.byref(layer), int(mode), C.byref(h)))
+    return h.value
+
+
+def ara_free_layer(ctx, handle: int) -> None:
+    _check(ctx, lib().ara_free_layer(ctx, int(handle)))
+
+
+def ara_run_prepared(ctx, yet_handle: int, layer_handles: Sequence[int], seeds: Sequence[int], trial_begin: int,
+                     trial_end: int, ylt_ptrs: Sequence[int], max_occ_ptrs=None, stream=None) -> None:
+    """ylt_ptrs / max_occ_ptrs: raw device addresses (ints) or tensors, one per layer."""
+    n = len(layer_handles)
+    hs = (C.c_int32 * n)(*layer_handles)
+    sd = (C.c_uint32 * n)(*[int(v) & 0xFFFFFFFF for v in seeds])
+    to_addr = lambda v: v if isinstance(v, int) else _ptr(v)
+    outs = (C.c_void_p * n)(*[to_addr(v) for v in ylt_ptrs])
+    om = None if max_occ_ptrs is None else (C.c_void_p * n)(*[None if v is None else to_addr(v) for v in max_occ_ptrs])
+    bufs = [v for v in ylt_ptrs if not isinstance(v, int)]
+    _check(ctx, lib().ara_run_prepared(ctx, int(yet_handle), hs, n, sd, int(trial_begin), int(trial_end), outs, om,
+                                       _stream(stream, *bufs)))
 
 
 def ara_risk_measures(ctx, ylt, return_periods: Iterable[float] = DEFAULT_RETURN_PERIODS, n_trials=None,

@@ -41,6 +41,16 @@ struct EltRec {
     double ded = 0, lim = 0, share = 0;
 };
 
+// A layer whose tables were built once (ara_prepare_layer) and are reused.
+struct PreparedRec {
+    bool live = false;
+    int mode = 0;
+    int32_t C = 0;
+    bool has_corr = false;
+    DevBuf mem;
+    ara::LayerDev dev;
+};
+
 // Pinned host + device slot pair used to pass per-call descriptors.
 struct StageSlot {
     void* host = nullptr;
@@ -61,6 +71,7 @@ struct ara_ctx {
     std::string err;
     std::vector<YetRec> yets;
     std::vector<EltRec> elts;
+    std::vector<PreparedRec> prepared;
     // grow-only workspaces
     DevBuf ws_tab;        // layer tables
     DevBuf ws_out;        // device staging for host outputs
@@ -315,6 +326,22 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     return ARA_OK;
 }
 
+ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, const YetDev& yd, int64_t t0, int64_t t1,
+                       const LayerDev* layers_dev, int32_t n_layers, int32_t maxJ, hipStream_t s)
+{
+    if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
+    if (mode == ARA_MODE_SURROGATE)
+        HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, layers_dev, n_layers, 0u, (const MlpFrag*)c->sur_frag.p,
+                                          (const uint32_t*)c->sur_mask.p, s));
+    else
+        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, layers_dev, n_layers, maxJ, 0u, s));
+    if (c->profiling) {
+        HIPCHK(c, hipEventRecord(c->k_stop, s));
+        c->have_timing = true;
+    }
+    return ARA_OK;
+}
+
 ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
                     uint32_t seed, int64_t t0, int64_t t1, float* const* ylt_outs, float* const* omax_outs,
                     void* hip_stream, bool allow_host_out)
@@ -392,23 +419,14 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
                 p.dev.omax = omax_outs[l];
             }
         }
+        p.dev.seed = seed;
         devs[l] = p.dev;
     }
     void* layers_dev = nullptr;
     StageSlot* sl2 = nullptr;
     if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl2))) return st;
     YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
-    if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
-    if (mode == ARA_MODE_SURROGATE)
-        HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, seed,
-                                          (const MlpFrag*)c->sur_frag.p, (const uint32_t*)c->sur_mask.p, s));
-    else
-        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, (const LayerDev*)layers_dev,
-                                n_layers, maxJ, seed, s));
-    if (c->profiling) {
-        HIPCHK(c, hipEventRecord(c->k_stop, s));
-        c->have_timing = true;
-    }
+    if ((st = launch_mode(c, mode, has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, maxJ, s))) return st;
     if ((st = release_stage(c, sl1, s))) return st;
     if ((st = release_stage(c, sl2, s))) return st;
     bool sync = false;
@@ -537,6 +555,7 @@ void ara_destroy(ara_ctx* c)
         dev_free(c, e.cw);
         dev_free(c, e.mean);
     }
+    for (auto& pl : c->prepared) dev_free(c, pl.mem);
     dev_free(c, c->ws_tab);
     dev_free(c, c->ws_out);
     dev_free(c, c->ws_sel);
@@ -752,6 +771,100 @@ ara_status ara_run_layers(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, 
     if (!c) return ARA_E_STATE;
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
     return run_impl(c, yh, layers, n_layers, mode, seed, 0, c->yets[yh].N, ylt_outs, nullptr, hip_stream, false);
+}
+
+
+ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode mode, int32_t* handle)
+{
+    if (!c) return ARA_E_STATE;
+    if (!handle || !layer) return fail(c, ARA_E_INVAL, "bad arguments to ara_prepare_layer");
+    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
+        return fail(c, ARA_E_INVAL, "unknown mode %d", (int)mode);
+    if (layer->n_elts < 1 || !layer->elt_handles) return fail(c, ARA_E_INVAL, "empty layer");
+    const int32_t h0 = layer->elt_handles[0];
+    if (h0 < 0 || h0 >= (int32_t)c->elts.size() || !c->elts[h0].live) return fail(c, ARA_E_STATE, "unknown XELT %d", h0);
+    YetRec pseudo;
+    pseudo.C = c->elts[h0].C;
+    std::vector<const EltRec*> es;
+    ara_status st = check_layer(c, pseudo, layer, es);
+    if (st) return st;
+    if ((st = begin_call(c, nullptr))) return st;
+    PreparedRec pr;
+    LayerPlan plan;
+    plan_layer(layer, es, plan);
+    const size_t bytes = table_bytes(mode, pseudo.C, plan);
+    if ((st = dev_alloc(c, pr.mem, bytes))) return st;
+    void* elts_dev = nullptr;
+    StageSlot* sl = nullptr;
+    if ((st = stage(c, plan.elts.data(), plan.elts.size() * sizeof(EltDev), nullptr, &elts_dev, &sl))) {
+        dev_free(c, pr.mem);
+        return st;
+    }
+    if ((st = build_tables(c, mode, pseudo.C, plan, (char*)pr.mem.p, (const EltDev*)elts_dev, nullptr))) return st;
+    if ((st = release_stage(c, sl, nullptr))) return st;
+    HIPCHK(c, hipStreamSynchronize(nullptr));
+    pr.live = true;
+    pr.mode = mode;
+    pr.C = pseudo.C;
+    pr.has_corr = plan.has_corr;
+    pr.dev = plan.dev;
+    c->prepared.push_back(pr);
+    *handle = (int32_t)c->prepared.size() - 1;
+    return end_call(c, nullptr);
+}
+
+ara_status ara_free_layer(ara_ctx* c, int32_t h)
+{
+    if (!c) return ARA_E_STATE;
+    if (h < 0 || h >= (int32_t)c->prepared.size() || !c->prepared[h].live)
+        return fail(c, ARA_E_STATE, "unknown prepared layer %d", h);
+    HIPCHK(c, hipDeviceSynchronize());
+    dev_free(c, c->prepared[h].mem);
+    c->prepared[h].live = false;
+    return ARA_OK;
+}
+
+ara_status ara_run_prepared(ara_ctx* c, int32_t yh, const int32_t* handles, int32_t n, const uint32_t* seeds,
+                            int64_t t0, int64_t t1, float* const* ylt_outs, float* const* max_occ_outs,
+                            void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
+    if (n < 1 || !handles || !seeds || !ylt_outs) return fail(c, ARA_E_INVAL, "bad arguments to ara_run_prepared");
+    const YetRec& y = c->yets[yh];
+    if (t0 < 0 || t1 > y.N || t0 > t1) return fail(c, ARA_E_RANGE, "trial range outside the YET");
+    std::vector<LayerDev> devs((size_t)n);
+    int mode = -1;
+    bool has_corr = false;
+    int32_t maxJ = 0;
+    for (int32_t l = 0; l < n; ++l) {
+        const int32_t h = handles[l];
+        if (h < 0 || h >= (int32_t)c->prepared.size() || !c->prepared[h].live)
+            return fail(c, ARA_E_STATE, "unknown prepared layer %d", h);
+        const PreparedRec& pr = c->prepared[h];
+        if (mode >= 0 && pr.mode != mode) return fail(c, ARA_E_INVAL, "prepared layers of different modes");
+        mode = pr.mode;
+        if (pr.C != y.C) return fail(c, ARA_E_INVAL, "prepared layer %d has catalog %d, the YET %d", h, pr.C, y.C);
+        if (!ylt_outs[l] || !is_device_ptr(ylt_outs[l])) return fail(c, ARA_E_INVAL, "output %d must be device memory", l);
+        devs[l] = pr.dev;
+        devs[l].ylt = ylt_outs[l];
+        devs[l].omax = max_occ_outs ? max_occ_outs[l] : nullptr;
+        devs[l].seed = seeds[l];
+        has_corr |= pr.has_corr;
+        maxJ = std::max(maxJ, pr.dev.J);
+    }
+    if (mode == ARA_MODE_SURROGATE && !c->sur_ready)
+        return fail(c, ARA_E_STATE, "surrogate mode needs a trained or imported surrogate");
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    void* layers_dev = nullptr;
+    StageSlot* sl = nullptr;
+    if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl))) return st;
+    YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
+    if ((st = launch_mode(c, mode, has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n, maxJ, s))) return st;
+    if ((st = release_stage(c, sl, s))) return st;
+    return end_call(c, s);
 }
 
 ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const double* rps, int32_t n_rp, double* pml,

@@ -35,8 +35,8 @@ struct LayerDev {
     float* omax;            // [trial_end - trial_begin] or null
     float occR, occL, aggR, aggL;
     uint32_t prog;
+    uint32_t seed;          // key word of this layer's random numbers
     int32_t J;
-    int32_t pad0;
     float4 jt[kMaxEltsPerLayer];   // per-XELT (deductible, limit, share, 0)
 };
 

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64
                     const uint32_t slot = (uint32_t)base + (meta & 63u);
                     const uint32_t j = meta >> 8;
                     const EntryRec E = L.pent[pi];
-                    const double z = draw_z<HAS_CORR>(tr, slot, j, seed, L.prog, L.pcw, pi);
+                    const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
                     const float loss = sample_loss(z, E);
                     const float4 jt = L.jt[j];
                     const float net = jt.z * xl(loss, jt.x, jt.y);       // per-XELT terms

@@ -441,7 +441,7 @@ __global__ __launch_bounds__(256) void k_layer_surrogate(YetDev y, int64_t t0, i
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const SurEntry SE = L.psur[pi];
                         if (SE.f0 >= flo && SE.f0 <= fhi && SE.f1 >= flo && SE.f1 <= fhi) {
-                            const double z = draw_z<HAS_CORR>(tr, slot, j, seed, L.prog, L.pcw, pi);
+                            const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
                             const float v = normcdfinvf((float)z);
                             const int cell = sur_cell(SE.f0, SE.f1, v);
                             is_sur = !((mask[cell >> 5] >> (cell & 31)) & 1u);
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(256) void k_layer_surrogate(YetDev y, int64_t t0, i
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
-                        const double z = draw_z<HAS_CORR>(tr, slot, j, seed, L.prog, L.pcw, pi);
+                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
                         const float loss = sample_loss(z, E);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);
