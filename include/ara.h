@@ -161,6 +161,19 @@ ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *lay
                             float *const *ylt_outs, float *const *max_occ_outs, void *hip_stream);
 
 /*
+ * Trial tile: the layer kernels evaluate one trial per 64-lane wavefront and
+ * group `wpb` wavefronts (1, 2, 4 or 8; 8 not in surrogate mode) per
+ * workgroup.  ara_set_trial_tile fixes it for a mode; ara_autotune times each
+ * choice on the first n_trials trials for the given prepared layers (all of
+ * one mode), keeps the fastest for that mode and returns it (ms_out,
+ * optional: the time of each candidate 1, 2, 4, 8, float [4]).  Results do not
+ * depend on the choice.
+ */
+ara_status ara_set_trial_tile(ara_ctx *ctx, ara_mode mode, int32_t wpb);
+ara_status ara_autotune(ara_ctx *ctx, int32_t yet_handle, const int32_t *layer_handles, int32_t n_layers,
+                        int64_t n_trials, int32_t *best_wpb_out, float *ms_out);
+
+/*
  * PML and TVaR (section 2.4) of a YLT of n_trials floats (device or host):
  * for each return period RP, k = floor(n_trials / RP) (ARA_E_RANGE if k < 1);
  * PML = the k-th largest year loss; TVaR = the mean of the k largest, summed in
@@ -248,6 +261,11 @@ ara_status ara_philox_uniforms(ara_ctx *ctx, const uint32_t *ctr, int64_t n, uin
                                float *out, void *hip_stream);
 ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                              double *x_out, void *hip_stream);
+/* ara_beta_quantile_layer: the per-draw inverse exactly as the plain layer
+ * kernel applies it -- the FP32 solve alone where min(a, b) >= 0.2, FP32 plus
+ * the FP64 polish below that.  Same arguments as ara_beta_quantile. */
+ara_status ara_beta_quantile_layer(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
+                                   double *x_out, void *hip_stream);
 
 #ifdef __cplusplus
 }

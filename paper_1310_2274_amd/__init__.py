@@ -74,6 +74,8 @@ def lib() -> C.CDLL:
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
             "ara_set_profiling": (i32, [vp, i32]),
             "ara_prepare_layer": (i32, [vp, C.POINTER(LayerDesc), C.c_int, C.POINTER(i32)]),
+            "ara_set_trial_tile": (i32, [vp, C.c_int, i32]),
+            "ara_autotune": (i32, [vp, i32, C.POINTER(i32), i32, i64, C.POINTER(i32), vp]),
             "ara_free_layer": (i32, [vp, i32]),
             "ara_run_prepared": (i32, [vp, i32, C.POINTER(i32), i32, C.POINTER(u32), i64, i64, C.POINTER(vp),
                                        C.POINTER(vp), vp]),
@@ -86,6 +88,7 @@ def lib() -> C.CDLL:
             "ara_surrogate_eval": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_last_kernel_ms": (i32, [vp, C.POINTER(C.c_double)]),
             "ara_beta_quantile": (i32, [vp, vp, vp, vp, i64, vp, vp]),
+            "ara_beta_quantile_layer": (i32, [vp, vp, vp, vp, i64, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -238,6 +241,20 @@ def ara_prepare_layer(ctx, layer: LayerDesc, mode: int) -> int:
     return h.value
 
 
+def ara_set_trial_tile(ctx, mode: int, wpb: int) -> None:
+    _check(ctx, lib().ara_set_trial_tile(ctx, int(mode), int(wpb)))
+
+
+def ara_autotune(ctx, yet_handle: int, layer_handles: Sequence[int], n_trials: int):
+    """Pick the fastest trial tile for these prepared layers; returns (best, ms per candidate 1/2/4/8)."""
+    n = len(layer_handles)
+    hs = (C.c_int32 * n)(*layer_handles)
+    best = C.c_int32()
+    ms = np.full(4, np.nan, dtype=np.float32)
+    _check(ctx, lib().ara_autotune(ctx, int(yet_handle), hs, n, int(n_trials), C.byref(best), ms.ctypes.data))
+    return best.value, ms
+
+
 def ara_free_layer(ctx, handle: int) -> None:
     _check(ctx, lib().ara_free_layer(ctx, int(handle)))
 
@@ -365,14 +382,20 @@ def ara_philox_uniforms(ctx, ctr, key0: int, key1: int, out=None, stream=None):
     return out
 
 
-def ara_beta_quantile(ctx, a, b, u, out=None, stream=None):
+def ara_beta_quantile_layer(ctx, a, b, u, out=None, stream=None):
+    """The per-draw inverse as the plain layer kernel applies it."""
+    return ara_beta_quantile(ctx, a, b, u, out, stream, _layer=True)
+
+
+def ara_beta_quantile(ctx, a, b, u, out=None, stream=None, _layer=False):
     if isinstance(a, np.ndarray) or np.isscalar(a):
         a, b, u = np.broadcast_arrays(np.asarray(a, np.float64), np.asarray(b, np.float64), np.asarray(u, np.float64))
         a, b, u = (np.ascontiguousarray(v) for v in (a, b, u))
     n = int(u.shape[0])
     if out is None:
         out = np.empty(n, dtype=np.float64)
-    _check(ctx, lib().ara_beta_quantile(ctx, _ptr(a), _ptr(b), _ptr(u), n, _ptr(out), _stream(stream, a, b, u, out)))
+    fn = lib().ara_beta_quantile_layer if _layer else lib().ara_beta_quantile
+    _check(ctx, fn(ctx, _ptr(a), _ptr(b), _ptr(u), n, _ptr(out), _stream(stream, a, b, u, out)))
     return out
 
 

@@ -89,6 +89,7 @@ struct ara_ctx {
     int64_t sur_step = 0;
     DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_loss;
     DevBuf sur_tuples, sur_gpart, sur_lpart, sur_calib;
+    int32_t wpb[3] = {4, 4, 4};     // trial tile (wavefronts per workgroup) per mode
     bool profiling = false;
     bool have_timing = false;
     hipEvent_t k_start = nullptr, k_stop = nullptr;
@@ -330,11 +331,13 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, const YetDev& yd, in
                        const LayerDev* layers_dev, int32_t n_layers, int32_t maxJ, hipStream_t s)
 {
     if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
+    (void)maxJ;
     if (mode == ARA_MODE_SURROGATE)
-        HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, layers_dev, n_layers, 0u, (const MlpFrag*)c->sur_frag.p,
-                                          (const uint32_t*)c->sur_mask.p, s));
+        HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, layers_dev, n_layers, (const MlpFrag*)c->sur_frag.p,
+                                          (const uint32_t*)c->sur_mask.p, c->wpb[mode], s));
     else
-        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, layers_dev, n_layers, maxJ, 0u, s));
+        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode],
+                                s));
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(c->k_stop, s));
         c->have_timing = true;
@@ -867,6 +870,61 @@ ara_status ara_run_prepared(ara_ctx* c, int32_t yh, const int32_t* handles, int3
     return end_call(c, s);
 }
 
+ara_status ara_set_trial_tile(ara_ctx* c, ara_mode mode, int32_t wpb)
+{
+    if (!c) return ARA_E_STATE;
+    if (mode < ARA_MODE_MEAN || mode > ARA_MODE_SURROGATE) return fail(c, ARA_E_INVAL, "unknown mode");
+    const bool ok = wpb == 1 || wpb == 2 || wpb == 4 || (wpb == 8 && mode != ARA_MODE_SURROGATE);
+    if (!ok) return fail(c, ARA_E_INVAL, "trial tile %d not available for mode %d", wpb, (int)mode);
+    c->wpb[mode] = wpb;
+    return ARA_OK;
+}
+
+ara_status ara_autotune(ara_ctx* c, int32_t yh, const int32_t* handles, int32_t n, int64_t n_trials,
+                        int32_t* best_out, float* ms_out)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 1 || !handles) return fail(c, ARA_E_INVAL, "bad arguments to ara_autotune");
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
+    if (handles[0] < 0 || handles[0] >= (int32_t)c->prepared.size() || !c->prepared[handles[0]].live)
+        return fail(c, ARA_E_STATE, "unknown prepared layer %d", handles[0]);
+    const int mode = c->prepared[handles[0]].mode;
+    const int64_t nt = std::max<int64_t>(1, std::min<int64_t>(n_trials, c->yets[yh].N));
+    // scratch outputs for the trial slice
+    ara_status st;
+    if ((st = ws_reserve(c, c->ws_out, (size_t)n * align256((size_t)nt * 4)))) return st;
+    std::vector<float*> outs((size_t)n);
+    for (int32_t l = 0; l < n; ++l) outs[l] = (float*)((char*)c->ws_out.p + (size_t)l * align256((size_t)nt * 4));
+    std::vector<uint32_t> seeds((size_t)n, 1u);
+    const int32_t cand[4] = {1, 2, 4, 8};
+    int32_t best = c->wpb[mode];
+    float best_ms = 1e30f;
+    const bool prof = c->profiling;
+    c->profiling = true;
+    for (int ci = 0; ci < 4; ++ci) {
+        if (cand[ci] == 8 && mode == ARA_MODE_SURROGATE) continue;
+        c->wpb[mode] = cand[ci];
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {      // first run warms up
+            if ((st = ara_run_prepared(c, yh, handles, n, seeds.data(), 0, nt, outs.data(), nullptr, nullptr))) {
+                c->profiling = prof;
+                return st;
+            }
+            HIPCHK(c, hipEventSynchronize(c->k_stop));
+            HIPCHK(c, hipEventElapsedTime(&ms, c->k_start, c->k_stop));
+        }
+        if (ms_out) ms_out[ci] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[ci];
+        }
+    }
+    c->profiling = prof;
+    c->wpb[mode] = best;
+    if (best_out) *best_out = best;
+    return ARA_OK;
+}
+
 ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const double* rps, int32_t n_rp, double* pml,
                              double* tvar, void* hip_stream)
 {
@@ -963,8 +1021,8 @@ ara_status ara_philox_uniforms(ara_ctx* c, const uint32_t* ctr, int64_t n, uint3
     return ARA_OK;
 }
 
-ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n, double* x,
-                             void* hip_stream)
+static ara_status beta_quantile_impl(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
+                                     double* x, void* hip_stream, bool layer)
 {
     if (!c) return ARA_E_STATE;
     if (n < 0 || (n > 0 && (!a || !b || !u || !x))) return fail(c, ARA_E_INVAL, "bad arguments to ara_beta_quantile");
@@ -995,7 +1053,8 @@ ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const
             q += nb;
         }
     double* xo = dx ? x : (double*)q;
-    HIPCHK(c, launch_beta_quantile(ptr[0], ptr[1], ptr[2], n, xo, s));
+    if (layer) HIPCHK(c, launch_beta_quantile_layer(ptr[0], ptr[1], ptr[2], n, xo, s));
+    else HIPCHK(c, launch_beta_quantile(ptr[0], ptr[1], ptr[2], n, xo, s));
     if (!dx) HIPCHK(c, hipMemcpyAsync(x, xo, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     if ((st = end_call(c, s))) return st;
     if (need) HIPCHK(c, hipStreamSynchronize(s));
@@ -1194,4 +1253,17 @@ ara_status ara_surrogate_eval(ara_ctx* c, const double* a, const double* b, cons
     if (used) HIPCHK(c, hipMemcpy(used, q + 4 * nb, (size_t)n * 4, hipMemcpyDeviceToHost));
     return end_call(c, nullptr);
 }
+
+ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n, double* x,
+                             void* hip_stream)
+{
+    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, false);
+}
+
+ara_status ara_beta_quantile_layer(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
+                                   double* x, void* hip_stream)
+{
+    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, true);
+}
+
 }  // extern "C"

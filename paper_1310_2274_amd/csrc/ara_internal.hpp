@@ -61,17 +61,19 @@ hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uin
                              EntryRec* pent, float2* pcw, hipStream_t s);
 hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,
                              float* occ_tab, hipStream_t s);
+// wpb: wavefronts (= trials) per workgroup, 1, 2, 4 or 8 -- the trial tile
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
-                         const LayerDev* layers, int32_t n_layers, int32_t max_J, uint32_t seed,
-                         hipStream_t s);
+                         const LayerDev* layers, int32_t n_layers, int32_t wpb, hipStream_t s);
 
 // ---- surrogate (ara_surrogate.hip) ----
 hipError_t launch_sur_entries(const EntryRec* pent, int64_t n, SurEntry* psur, hipStream_t s);
 hipError_t launch_layers_surrogate(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                                   int32_t n_layers, uint32_t seed, const MlpFrag* frag, const uint32_t* cellmask,
+                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, int32_t wpb,
                                    hipStream_t s);
 
 hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s);
+hipError_t launch_beta_quantile_layer(const double* a, const double* b, const double* u, int64_t n, double* x,
+                                      hipStream_t s);
 hipError_t launch_beta_quantile(const double* a, const double* b, const double* u, int64_t n, double* x, hipStream_t s);
 
 struct SelectWs {

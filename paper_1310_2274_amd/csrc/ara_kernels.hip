@@ -194,21 +194,32 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t
 // ===========================================================================
 constexpr int kWavesPerBlock = 4;
 constexpr int kChunk = 64;                   // event slots per compaction round
-constexpr int kRound = 16;                   // draws per slot per drain round
+constexpr int kRound = 8;                    // draws per slot per drain round
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 
-template <bool HAS_CORR>
-__global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
-                                                     const LayerDev* __restrict__ layers, int32_t n_layers,
-                                                     uint32_t seed)
+// One drain round of the plain path: the queued draws are split into those
+// the FP32 solve handles alone and those that need the FP64 polish (small
+// shape parameters, degenerate entries), and each list is drained 64 draws at
+// a time so a wave's lanes share one cost class.  Each draw's net loss lands
+// at its queue position.
+template <bool HAS_CORR, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+                                                          const LayerDev* __restrict__ layers, int32_t n_layers)
 {
-    __shared__ uint32_t qbuf[kWavesPerBlock][2][kQueue];
+    __shared__ uint32_t qidx[WPB][kQueue];
+    __shared__ uint32_t qmeta[WPB][kQueue];
+    __shared__ float qv[WPB][kQueue];
+    __shared__ uint16_t lst[WPB][2][kQueue];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t trial = t0 + (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
     if (trial >= t1) return;
-    uint32_t* qidx = qbuf[w][0];     // packed entry index, then the draw's net loss
-    uint32_t* qmeta = qbuf[w][1];    // slot within chunk | XELT position << 8
+    uint32_t* QI = qidx[w];          // packed entry index
+    uint32_t* QM = qmeta[w];         // slot within chunk | XELT position << 8
+    float* QV = qv[w];               // the draw's net loss
+    uint16_t* L32 = lst[w][0];
+    uint16_t* L64 = lst[w][1];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     int64_t row;
     int32_t len;
@@ -237,24 +248,60 @@ __global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64
                 for (int i = 0; i < take; ++i) {
                     const int j = __ffsll((unsigned long long)mask) - 1;
                     mask &= mask - 1;
-                    qidx[pos + i] = off + (uint32_t)(rank + i);
-                    qmeta[pos + i] = (uint32_t)lane | ((uint32_t)j << 8);
+                    QI[pos + i] = off + (uint32_t)(rank + i);
+                    QM[pos + i] = (uint32_t)lane | ((uint32_t)j << 8);
                 }
                 wave_sync();
-                for (int q = lane; q < total; q += 64) {
-                    const uint32_t pi = qidx[q];
-                    const uint32_t meta = qmeta[q];
-                    const uint32_t slot = (uint32_t)base + (meta & 63u);
-                    const uint32_t j = meta >> 8;
-                    const EntryRec E = L.pent[pi];
-                    const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                    const float loss = sample_loss(z, E);
-                    const float4 jt = L.jt[j];
-                    const float net = jt.z * xl(loss, jt.x, jt.y);       // per-XELT terms
-                    qidx[q] = __float_as_uint(net);
+                // (A) classify
+                int n32 = 0, n64 = 0;
+                for (int b0 = 0; b0 < total; b0 += 64) {
+                    const int q = b0 + lane;
+                    const bool in = q < total;
+                    bool pol = false;
+                    if (in) {
+                        const EntryRec& E = L.pent[QI[q]];
+                        pol = fmin(E.a, E.b) < kPolishShape;
+                    }
+                    const uint64_t b64 = __ballot(in && pol);
+                    const uint64_t b32 = __ballot(in && !pol);
+                    if (in) {
+                        if (pol) L64[n64 + __popcll(b64 & below)] = (uint16_t)q;
+                        else L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
+                    }
+                    n64 += __popcll(b64);
+                    n32 += __popcll(b32);
                 }
                 wave_sync();
-                for (int i = 0; i < take; ++i) c += __uint_as_float(qidx[pos + i]);
+                // (B) FP32 solve
+                for (int b0 = 0; b0 < n32; b0 += 64) {
+                    const int idx = b0 + lane;
+                    if (idx < n32) {
+                        const int q = L32[idx];
+                        const uint32_t pi = QI[q], meta = QM[q];
+                        const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
+                        const EntryRec E = L.pent[pi];
+                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        const float loss = E.maxl * inv_beta32((float)z, E);
+                        const float4 jt = L.jt[j];
+                        QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
+                    }
+                }
+                // (C) FP32 solve + FP64 polish, and degenerate entries
+                for (int b0 = 0; b0 < n64; b0 += 64) {
+                    const int idx = b0 + lane;
+                    if (idx < n64) {
+                        const int q = L64[idx];
+                        const uint32_t pi = QI[q], meta = QM[q];
+                        const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
+                        const EntryRec E = L.pent[pi];
+                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        const float loss = sample_loss(z, E);
+                        const float4 jt = L.jt[j];
+                        QV[q] = jt.z * xl(loss, jt.x, jt.y);
+                    }
+                }
+                wave_sync();
+                for (int i = 0; i < take; ++i) c += QV[pos + i];
                 rank += take;
                 remaining -= take;
                 wave_sync();
@@ -277,12 +324,13 @@ __global__ __launch_bounds__(256) void k_layer_plain(YetDev y, int64_t t0, int64
 
 // Mean mode: stream the event ids (16-byte loads when the rows allow it) and
 // gather the tabulated occurrence loss; HBM-bound.
-__global__ __launch_bounds__(256) void k_layer_mean(YetDev y, int64_t t0, int64_t t1,
-                                                    const LayerDev* __restrict__ layers, int32_t n_layers)
+template <int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_layer_mean(YetDev y, int64_t t0, int64_t t1,
+                                                         const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t trial = t0 + (int64_t)blockIdx.x * kWavesPerBlock + w;
+    const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
     if (trial >= t1) return;
     int64_t row;
     int32_t len;
@@ -456,9 +504,31 @@ __global__ void k_beta_quantile(const double* __restrict__ a, const double* __re
     x[i] = inv_beta(u[i], E);
 }
 
+__global__ void k_beta_quantile_layer(const double* __restrict__ a, const double* __restrict__ b,
+                                      const double* __restrict__ u, int64_t n, double* __restrict__ x)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    EntryRec E;
+    E.a = a[i];
+    E.b = b[i];
+    E.lnB = log_beta(E.a, E.b);
+    E.us = (float)beta_inc_lower((E.a + 1.0) / (E.a + E.b + 2.0), E.a, E.b, E.lnB);
+    E.maxl = 1.0f;
+    x[i] = inv_beta_layer(u[i], E);
+}
+
 // ===========================================================================
 // Launchers
 // ===========================================================================
+hipError_t launch_beta_quantile_layer(const double* a, const double* b, const double* u, int64_t n, double* x,
+                                      hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_beta_quantile_layer, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, s, a, b, u, n, x);
+    return hipGetLastError();
+}
+
 hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s)
 {
     if (n > 0)
@@ -531,18 +601,30 @@ hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double oc
     return hipGetLastError();
 }
 
-hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                         int32_t n_layers, int32_t /*max_J*/, uint32_t seed, hipStream_t s)
+template <int WPB>
+static void launch_layers_wpb(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
+                              int32_t n_layers, hipStream_t s)
 {
     const int64_t n = t1 - t0;
-    if (n <= 0 || n_layers <= 0) return hipSuccess;
-    const dim3 grid(nblocks(n, kWavesPerBlock)), block(64 * kWavesPerBlock);
+    const dim3 grid(nblocks(n, WPB)), block(64 * WPB);
     if (mode == 0)
-        hipLaunchKernelGGL(k_layer_mean, grid, block, 0, s, y, t0, t1, layers, n_layers);
+        hipLaunchKernelGGL(k_layer_mean<WPB>, grid, block, 0, s, y, t0, t1, layers, n_layers);
     else if (has_corr)
-        hipLaunchKernelGGL(k_layer_plain<true>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed);
+        hipLaunchKernelGGL((k_layer_plain<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
     else
-        hipLaunchKernelGGL(k_layer_plain<false>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed);
+        hipLaunchKernelGGL((k_layer_plain<false, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+}
+
+hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
+                         int32_t n_layers, int32_t wpb, hipStream_t s)
+{
+    if (t1 - t0 <= 0 || n_layers <= 0) return hipSuccess;
+    switch (wpb) {
+        case 1: launch_layers_wpb<1>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
+        case 2: launch_layers_wpb<2>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
+        case 8: launch_layers_wpb<8>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
+        default: launch_layers_wpb<4>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
+    }
     return hipGetLastError();
 }
 

@@ -229,6 +229,54 @@ __host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaS
     return lower ? exp(yd) : -expm1(yd);
 }
 
+// Draws whose smaller shape parameter is below this take the FP64 polish; at
+// or above it the FP32 solve alone is accurate to a few 1e-6 relative (the
+// quantile's sensitivity to an error in ln I grows like 1/shape).
+constexpr double kPolishShape = 0.2;
+
+__host__ __device__ inline bool needs_polish(const EntryRec& E)
+{
+    return (E.a < E.b ? E.a : E.b) < kPolishShape;
+}
+
+// FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape):
+// the same log-space Newton iteration as inv_beta, run to the FP32 noise floor
+// with hardware exp/log and approximate divisions.  Device only.
+__device__ inline float inv_beta32(float z, const EntryRec& E)
+{
+    const bool lower = z <= E.us;
+    const float A = (float)(lower ? E.a : E.b);
+    const float B = (float)(lower ? E.b : E.a);
+    const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
+    const float lnp = __logf(p);
+    const float c0 = (float)(-(E.lnB + log(lower ? E.a : E.b)));
+    const float ts = __fdividef(A + 1.0f, A + B + 2.0f);
+    const float lts = __logf(ts);
+    const float ymax = __logf(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    float y = fminf(__fdividef(lnp - c0, A), lts);
+    const float yfloor = lower ? -110.0f : -40.0f;
+    for (int it = 0; it < 10 && y > yfloor; ++it) {
+        const float t = __expf(y);
+        const float l1t = log1pf(-t);
+        float num, den;
+        beta_cf<float>(t, A, B, 2e-7f, 48, num, den);
+        const float f = A * y + B * l1t + c0 + __logf(__fdividef(den, num)) - lnp;
+        const float dy = -__fdividef(f * (1.0f - t) * den, A * num);
+        const float yn = fminf(y + dy, ymax);
+        const float step = yn - y;
+        y = yn;
+        if (fabsf(step) <= 4e-6f * fmaxf(1.0f, fabsf(y))) break;
+    }
+    return lower ? __expf(y) : -expm1f(y);
+}
+
+// The inverse the plain layer kernel applies to one draw.
+__device__ inline double inv_beta_layer(double z, const EntryRec& E)
+{
+    if (needs_polish(E)) return inv_beta(z, E);
+    return (double)inv_beta32((float)z, E);
+}
+
 // Sampled loss of one draw: max_l * InvCDF_beta(z; alpha, beta) (section 3.3).
 __host__ __device__ inline float sample_loss(double z, const EntryRec& E)
 {

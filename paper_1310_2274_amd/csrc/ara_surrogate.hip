@@ -374,25 +374,25 @@ __global__ void k_sur_entries(const EntryRec* __restrict__ pent, int64_t n, SurE
 constexpr int kSurRound = 8;
 constexpr int kSurQueue = 64 * kSurRound;
 
-template <bool HAS_CORR>
-__global__ __launch_bounds__(256) void k_layer_surrogate(YetDev y, int64_t t0, int64_t t1,
-                                                         const LayerDev* __restrict__ layers, int32_t n_layers,
-                                                         uint32_t seed, const MlpFrag* __restrict__ Fg,
-                                                         const uint32_t* __restrict__ gmask)
+template <bool HAS_CORR, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t t0, int64_t t1,
+                                                              const LayerDev* __restrict__ layers, int32_t n_layers,
+                                                              const MlpFrag* __restrict__ Fg,
+                                                              const uint32_t* __restrict__ gmask)
 {
     __shared__ MlpFrag F;
     __shared__ uint32_t mask[kCells / 32];
-    __shared__ uint32_t qidx[4][kSurQueue];
-    __shared__ uint32_t qmeta[4][kSurQueue];
-    __shared__ float qv[4][kSurQueue];
-    __shared__ uint16_t lst[4][2][kSurQueue];
+    __shared__ uint32_t qidx[WPB][kSurQueue];
+    __shared__ uint32_t qmeta[WPB][kSurQueue];
+    __shared__ float qv[WPB][kSurQueue];
+    __shared__ uint16_t lst[WPB][2][kSurQueue];
     copy_frag_to_lds(Fg, F);
     for (int w = threadIdx.x; w < kCells / 32; w += blockDim.x) mask[w] = gmask[w];
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t trial = t0 + (int64_t)blockIdx.x * 4 + w;
-    // waves past the end still take part in no block-wide barrier below
+    const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
+    // waves past the end take part in no block-wide barrier below
     if (trial >= t1) return;
     uint32_t* QI = qidx[w];
     uint32_t* QM = qmeta[w];
@@ -520,17 +520,28 @@ hipError_t launch_sur_entries(const EntryRec* pent, int64_t n, SurEntry* psur, h
     return hipGetLastError();
 }
 
+template <int WPB>
+static void launch_sur_wpb(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
+                           int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, hipStream_t s)
+{
+    const dim3 grid(grid_for(t1 - t0, WPB)), block(64 * WPB);
+    if (has_corr)
+        hipLaunchKernelGGL((k_layer_surrogate<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers, frag, cellmask);
+    else
+        hipLaunchKernelGGL((k_layer_surrogate<false, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers, frag,
+                           cellmask);
+}
+
 hipError_t launch_layers_surrogate(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                                   int32_t n_layers, uint32_t seed, const MlpFrag* frag, const uint32_t* cellmask,
+                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, int32_t wpb,
                                    hipStream_t s)
 {
-    const int64_t n = t1 - t0;
-    if (n <= 0 || n_layers <= 0) return hipSuccess;
-    const dim3 grid(grid_for(n, 4)), block(256);
-    if (has_corr)
-        hipLaunchKernelGGL(k_layer_surrogate<true>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed, frag, cellmask);
-    else
-        hipLaunchKernelGGL(k_layer_surrogate<false>, grid, block, 0, s, y, t0, t1, layers, n_layers, seed, frag, cellmask);
+    if (t1 - t0 <= 0 || n_layers <= 0) return hipSuccess;
+    switch (wpb) {
+        case 1: launch_sur_wpb<1>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
+        case 2: launch_sur_wpb<2>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
+        default: launch_sur_wpb<4>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
+    }
     return hipGetLastError();
 }
 

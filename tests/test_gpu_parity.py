@@ -86,6 +86,22 @@ def test_beta_quantile_paper_scale_parameters(eng):
     assert np.max(np.abs(x[visible] - xo[visible]) / xo[visible]) <= 1e-8
 
 
+@pytest.mark.parametrize("lo,hi,seed", [(1e-3, 40.0, 5), (0.2, 50.0, 6)])
+def test_layer_inverse_per_draw_accuracy(eng, lo, hi, seed):
+    # the inverse exactly as the plain layer kernel applies it: FP32 alone
+    # where min(a, b) >= 0.2 (a few 1e-6 relative), FP32 + FP64 polish below
+    a, b, u = _grid(40000, lo, hi, seed)
+    x = P.ara_beta_quantile_layer(eng.ctx, a, b, u)
+    xo = oracle.beta_inc_inv_vec(u, a, b, threads=0)
+    visible = xo > 1e-30
+    rel = np.abs(x - xo) / np.maximum(xo, 1e-300)
+    fp32 = np.minimum(a, b) >= 0.2
+    assert np.all(rel[visible & fp32] <= 1e-5), rel[visible & fp32].max()
+    assert np.quantile(rel[visible & fp32], 0.99) <= 2e-6
+    assert np.all(rel[visible & ~fp32] <= 1e-8)
+    assert np.all(x[~visible] <= 1e-28)
+
+
 def test_beta_quantile_rejects_bad_input(eng):
     with pytest.raises(P.AraError) as e:
         P.ara_beta_quantile(eng.ctx, np.array([1.0]), np.array([-1.0]), np.array([0.5]))
@@ -313,3 +329,31 @@ def test_hbm_budget_refusal():
         assert P.ara_bytes_in_use(e.ctx) < (8 << 20)
         h = P.ara_load_yet(e.ctx, np.zeros((16, 16), dtype=np.int32), 10)
         assert h >= 0
+
+
+def test_trial_tile_does_not_change_results_and_autotune(eng):
+    torch = torch_cuda()
+    wl = synth.portfolio(n_layers=3, n_trials=2000)
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    for mode in (P.MODE_MEAN, P.MODE_PLAIN):
+        hs = [P.ara_prepare_layer(eng.ctx, eng.load_layer(l, wl.catalog_size), mode) for l in wl.layers]
+        ref = None
+        for wpb in (1, 2, 4, 8):
+            P.ara_set_trial_tile(eng.ctx, mode, wpb)
+            outs = [torch.empty(wl.n_trials, device="cuda") for _ in hs]
+            P.ara_run_prepared(eng.ctx, yh, hs, [5, 6, 7], 0, wl.n_trials, outs)
+            torch.cuda.synchronize()
+            got = torch.stack(outs).cpu().numpy()
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), (mode, wpb)
+        best, ms = P.ara_autotune(eng.ctx, yh, hs, 2000)
+        assert best in (1, 2, 4, 8) and np.isfinite(ms).all()
+        # prepared runs equal the one-shot call
+        single = torch.empty(wl.n_trials, device="cuda")
+        P.ara_run_layer_ex(eng.ctx, yh, eng.load_layer(wl.layers[1], wl.catalog_size), mode, 6, 0, wl.n_trials, single)
+        torch.cuda.synchronize()
+        assert np.array_equal(single.cpu().numpy(), ref[1])
+        for h in hs:
+            P.ara_free_layer(eng.ctx, h)
+        P.ara_set_trial_tile(eng.ctx, mode, 4)
