@@ -6,7 +6,7 @@ ln b / 2, Phi^-1(u) / 3), base = psi(a) - psi(b) + sqrt(psi'(a) + psi'(b))
 Phi^-1(u) -- the prediction is
 
     x_hat = sigmoid(base + w3 . g(W2 g(W1 f + b1) + b2) + b3),
-    g(z)  = z * sigmoid(1.702 z),
+    g(z)  = z * S(z),  S(z) = smoothstep(clamp(z/5 + 1/2, 0, 1)) = u^2 (3 - 2u),
 
 and the loss is the mean squared error of x_hat against x.  The flat parameter
 vector is W1 [64][3], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 (4481
@@ -36,12 +36,13 @@ def sigmoid(z):
 
 
 def g(z):
-    return z * sigmoid(1.702 * z)
+    u = np.clip(z / 5.0 + 0.5, 0.0, 1.0)
+    return z * u * u * (3.0 - 2.0 * u)
 
 
 def g_prime(z):
-    s = sigmoid(1.702 * z)
-    return s + 1.702 * z * s * (1.0 - s)
+    u = np.clip(z / 5.0 + 0.5, 0.0, 1.0)
+    return u * u * (3.0 - 2.0 * u) + z * 1.2 * u * (1.0 - u)
 
 
 def forward(P, T):

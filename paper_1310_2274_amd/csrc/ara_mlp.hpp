@@ -8,7 +8,9 @@
 //             m + s v,  m = psi(a) - psi(b),  s = sqrt(psi'(a) + psi'(b))
 //             (ln(X/(1-X)) for X ~ Beta(a,b) is a difference of log-gamma
 //             variates with exactly this mean and variance)
-//   network   o = w3 . g(W2 g(W1 f + b1) + b2) + b3,  g(z) = z sigmoid(1.702 z)
+//   network   o = w3 . g(W2 g(W1 f + b1) + b2) + b3,  g(z) = z S(z), with S a
+//             piecewise-cubic stand-in for the Gaussian CDF of GELU:
+//             S(z) = smoothstep(clamp(z/5 + 1/2, 0, 1)) = u^2 (3 - 2u)
 //   output    x = sigmoid(m + s v + o)
 // so the network learns a residual in logit space.  Weights are kept in FP32
 // (training master copy) and used rounded to BF16; activations are FP16 and
@@ -40,12 +42,28 @@ constexpr float kVLim = 5.5f;              // |Phi^-1(u)| < 5.34 on the 2^-24 gr
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ inline float gelu_s(float z) { return z / (1.0f + expf(-1.702f * z)); }
-// derivative of z sigmoid(k z): sigma + k z sigma (1 - sigma)
+// activation g(z) = z S(z) and its derivative S(z) + z S'(z), in FP32 (training)
+__host__ __device__ inline float gelu_s(float z)
+{
+    const float u = fminf(fmaxf(z * 0.2f + 0.5f, 0.0f), 1.0f);
+    return z * (u * u * (3.0f - 2.0f * u));
+}
 __host__ __device__ inline float gelu_s_grad(float z)
 {
-    const float s = 1.0f / (1.0f + expf(-1.702f * z));
-    return s + 1.702f * z * s * (1.0f - s);
+    const float u = fminf(fmaxf(z * 0.2f + 0.5f, 0.0f), 1.0f);
+    return u * u * (3.0f - 2.0f * u) + z * (1.2f * u * (1.0f - u));
+}
+
+// the same activation on two FP16 values at once (inference)
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+__device__ inline h2 gelu_h2(h2 z)
+{
+    const h2 half = {(_Float16)0.5f, (_Float16)0.5f}, fifth = {(_Float16)0.2f, (_Float16)0.2f};
+    const h2 zero = {(_Float16)0.0f, (_Float16)0.0f}, one = {(_Float16)1.0f, (_Float16)1.0f};
+    const h2 three = {(_Float16)3.0f, (_Float16)3.0f}, mtwo = {(_Float16)-2.0f, (_Float16)-2.0f};
+    h2 u = z * fifth + half;
+    u = __builtin_elementwise_min(__builtin_elementwise_max(u, zero), one);
+    return z * (u * u * (u * mtwo + three));
 }
 
 // ---- digamma and trigamma (asymptotic series after the recurrences
@@ -170,6 +188,25 @@ __device__ inline void mlp_build_frag_lane(const float* __restrict__ P, MlpFrag&
     if (l == 0) F.b3 = (float)bf16_round_to_h(P[kOffB3]);
 }
 
+// g applied to two FP32 accumulator quads, packed as the 8 FP16 K slots of
+// the next B operand (first quad -> slots 0..3, second -> 4..7)
+__device__ inline h8 act_pack(const f4& a, const f4& b)
+{
+    h2 p[4];
+    p[0] = h2{(_Float16)a[0], (_Float16)a[1]};
+    p[1] = h2{(_Float16)a[2], (_Float16)a[3]};
+    p[2] = h2{(_Float16)b[0], (_Float16)b[1]};
+    p[3] = h2{(_Float16)b[2], (_Float16)b[3]};
+    h8 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const h2 g = gelu_h2(p[i]);
+        r[2 * i] = g[0];
+        r[2 * i + 1] = g[1];
+    }
+    return r;
+}
+
 // Residual o for the 64 draws of a wave: lane L supplies draw L's features
 // and receives draw L's output.  F lives in LDS.
 __device__ inline float mlp_forward64(const MlpFrag& F, float f0, float f1, float f2)
@@ -193,11 +230,7 @@ __device__ inline float mlp_forward64(const MlpFrag& F, float f0, float f1, floa
         for (int s = 0; s < 2; ++s) {
             const f4 z0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w1[2 * s][l], x, f4{0, 0, 0, 0}, 0, 0, 0);
             const f4 z1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w1[2 * s + 1][l], x, f4{0, 0, 0, 0}, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                h1[s][r] = (_Float16)gelu_s(z0[r]);
-                h1[s][4 + r] = (_Float16)gelu_s(z1[r]);
-            }
+            h1[s] = act_pack(z0, z1);
         }
         f4 z2[4];
 #pragma unroll
@@ -207,17 +240,12 @@ __device__ inline float mlp_forward64(const MlpFrag& F, float f0, float f1, floa
             acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w2[I][1][l], h1[1], acc, 0, 0, 0);
             z2[I] = acc;
         }
-        h8 h2[2];
+        h8 hb[2];
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                h2[s][r] = (_Float16)gelu_s(z2[2 * s][r]);
-                h2[s][4 + r] = (_Float16)gelu_s(z2[2 * s + 1][r]);
-            }
+        for (int s = 0; s < 2; ++s) hb[s] = act_pack(z2[2 * s], z2[2 * s + 1]);
         f4 o = {F.b3, F.b3, F.b3, F.b3};
-        o = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w3[0][l], h2[0], o, 0, 0, 0);
-        o = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w3[1][l], h2[1], o, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w3[0][l], hb[0], o, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_f16(F.w3[1][l], hb[1], o, 0, 0, 0);
         // row 0 of the output tile sits in register 0 of lanes 0..15
         const float oj = __shfl(o[0], l & 15, 64);
         if ((l >> 4) == J) out = oj;
