@@ -29,16 +29,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations/s
-# (one FP32 or FP64 FMA per lane per clock without packed math).
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU lane-operations per draw of the plain layer kernel on this workload,
+# VALU issue peak in lane-instructions/s: MI355X's FP32 vector rate of
+# 157.3 TFLOP/s counts an FMA as two flops, i.e. 78.6e12 FP32 lane-instructions
+# per second (256 CUs x 128 lanes x 2.4 GHz).  SQ_INSTS_VALU x 64 counts every
+# VALU instruction once, so FP64 and transcendental instructions, which issue
+# at lower rates, make the achieved figure an underestimate, never an overcount.
+PEAK_VALU_TOPS = 157.3 / 2
+# VALU lane-instructions per draw of the plain layer kernel on this workload,
 # SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 3215.0
-# HBM bytes per launch of the plain layer kernel at 800,000 trials: FETCH_SIZE
-# (x2, copy-kernel calibration) + WRITE_SIZE, measured on the 100,000-trial
-# slice and scaled by 8 (profiles/k_layer_plain_paper100k_counters.md).
-TRAFFIC_BYTES = 8 * (2 * 12787253.8 + 1188.5) * 1024
+VALU_OPS_PER_DRAW = 1787.1
+# Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
+# the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
+# measured on the 100,000-trial slice and scaled by 8.
+TRAFFIC_BYTES = 8 * (2 * 17441621.0 + 2027.4) * 1024
 
 
 def log(msg):
@@ -171,6 +174,20 @@ def serving_leg(P, torch, synth, rate, n_warm, n_meas, mode_name):
     return st
 
 
+def copy_probe():
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    readings give the factors that turn those counters into bytes."""
+    import torch
+    n = 256 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,10 +205,16 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB three times (FETCH_SIZE/WRITE_SIZE calibration under rocprofv3)")
     args = ap.parse_args()
 
+    if args.copy_probe:
+        copy_probe()
+        return
+
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "bench.py measures one GPU: the path has no multi-GPU mode, run with --gpus 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

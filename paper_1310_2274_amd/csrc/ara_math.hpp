@@ -109,8 +109,8 @@ __host__ __device__ inline void beta_cf(R t, R A, R B, R eps, int max_pairs, R& 
     R d2 = 0, d1 = 1;     // denominators X_{-1}, X_0
     R qprev = 1;
     const R apb = A + B;
-    for (int m = 0; m < max_pairs; ++m) {
-        const R fm = (R)m;
+    R fm = 0;                              // m, carried in R (no integer conversions)
+    for (int m = 0; m < max_pairs; ++m, fm += 1) {
         // n = 2m+1
         const R qo = (A + 2 * fm) * (A + 2 * fm + 1);
         const R po = -(A + fm) * (apb + fm) * t;
@@ -240,32 +240,57 @@ __host__ __device__ inline bool needs_polish(const EntryRec& E)
 }
 
 // FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape):
-// the same log-space Newton iteration as inv_beta, run to the FP32 noise floor
-// with hardware exp/log and approximate divisions.  Device only.
+// the same log-space Newton iteration as inv_beta, in FP32 with the hardware
+// exp2/log2/reciprocal (1 ulp each).  ln(1 - t) uses Goldberg's correction
+// ln(w) * t / (1 - w) with w = fl(1 - t), which is accurate to a few ulps
+// without an extended-precision log1p.  The loop stops once a step moves the
+// quantile x by less than 5e-4 relative: Newton's quadratic convergence then
+// leaves a relative error of order 1e-6 in x.  Device only.
+__device__ __forceinline__ float hw_ln(float x)      // x > 0 and normal
+{
+    return __builtin_amdgcn_logf(x) * 0.6931471805599453f;
+}
+__device__ __forceinline__ float hw_rcp(float x)
+{
+    return __builtin_amdgcn_rcpf(x);
+}
+
 __device__ inline float inv_beta32(float z, const EntryRec& E)
 {
     const bool lower = z <= E.us;
     const float A = (float)(lower ? E.a : E.b);
     const float B = (float)(lower ? E.b : E.a);
     const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
-    const float lnp = __logf(p);
-    const float c0 = (float)(-(E.lnB + log(lower ? E.a : E.b)));
-    const float ts = __fdividef(A + 1.0f, A + B + 2.0f);
-    const float lts = __logf(ts);
-    const float ymax = __logf(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
-    float y = fminf(__fdividef(lnp - c0, A), lts);
+    const float lnp = hw_ln(p);
+    const float rA = hw_rcp(A);
+    const float c0 = -((float)E.lnB + hw_ln(A));
+    const float ts = (A + 1.0f) * hw_rcp(A + B + 2.0f);
+    const float lts = hw_ln(ts);
+    const float ymax = hw_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    // Start: ln I_t = A y + c0 + g(t) with g(t) = B ln(1-t) - ln T(t), which
+    // vanishes at t = 0 and equals ln I_ts - A ln ts - c0 at ts (I_ts is
+    // stored).  Taking g linear in t and evaluating it at the leading-term
+    // root gives one cheap fixed-point step that brings the draws near ts,
+    // where the leading term alone is worst, within one Newton step.
+    float y = fminf((lnp - c0) * rA, lts);
+    const float gs = hw_ln(lower ? E.us : 1.0f - E.us) - A * lts - c0;
+    y = fminf((lnp - c0 - gs * __expf(y) * hw_rcp(ts)) * rA, lts);
     const float yfloor = lower ? -110.0f : -40.0f;
     for (int it = 0; it < 10 && y > yfloor; ++it) {
         const float t = __expf(y);
-        const float l1t = log1pf(-t);
+        const float w = 1.0f - t;
+        const float l1t = (w == 1.0f) ? -t : hw_ln(w) * (t * hw_rcp(1.0f - w));
         float num, den;
         beta_cf<float>(t, A, B, 2e-7f, 48, num, den);
-        const float f = A * y + B * l1t + c0 + __logf(__fdividef(den, num)) - lnp;
-        const float dy = -__fdividef(f * (1.0f - t) * den, A * num);
+        const float rnum = hw_rcp(num);
+        const float f = A * y + B * l1t + c0 + hw_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
+        const float dy = -(f * w * den) * (rA * rnum);
         const float yn = fminf(y + dy, ymax);
         const float step = yn - y;
         y = yn;
-        if (fabsf(step) <= 4e-6f * fmaxf(1.0f, fabsf(y))) break;
+        // a step dy moves x by dy (lower side, x = t) or by dy * t / (1 - t)
+        // relative to x (upper side, x = 1 - t)
+        if (fabsf(step) * (lower ? 1.0f : t * hw_rcp(w)) <= 5e-4f) break;
     }
     return lower ? __expf(y) : -expm1f(y);
 }
