@@ -229,17 +229,21 @@ ara_status ara_last_kernel_ms(ara_ctx *ctx, double *ms_out);
  * Training continues from the current weights (fresh weights on the first
  * call).  epoch_loss_out (optional, host, epochs doubles): mean squared error
  * in x per epoch.
- * ara_surrogate_calibrate: fills the error table from n_val fresh held-out
- * tuples and marks cells whose largest error exceeds tol (or that saw no
- * point) for fallback.  Outputs (optional, host): per-cell largest |error|
- * and mean signed error (float [4096] each), number of marked cells.
+ * Training clears the region table (bias and fallback marks).
+ * ara_surrogate_calibrate: fills the region table from n_val fresh held-out
+ * tuples: each cell's mean signed error becomes its bias, which inference
+ * subtracts from x, and cells whose largest error after that correction
+ * exceeds tol (or that saw no point) are marked for fallback to the exact
+ * inverse.  Outputs (optional, host): per-cell largest |error| after the
+ * correction and the bias (float [4096] each), number of marked cells.
  * ara_surrogate_grad: loss and gradient (float [4481], host) of the mean
  * squared error over n host tuples (f0, f1, f2, base, x; n a multiple of 64,
  * <= 65536) at the current weights, without an update (gradient checks).
  * ara_surrogate_tuples: n training tuples for seed (host float [n][5]).
  * ara_surrogate_export / _import: FP32 weights (float [4481]), Adam moments
- * (float [4481] each), step count and fallback mask (uint8 [4096]); any
- * pointer may be NULL.  Import makes the surrogate ready.
+ * (float [4481] each), step count, fallback mask (uint8 [4096]) and region
+ * bias (float [4096], |bias| <= 1); any pointer but the weights' may be NULL
+ * (a NULL mask or bias imports as all zero).  Import makes the surrogate ready.
  * ara_surrogate_eval: x[i] for host (a, b, u) arrays, through the same
  * surrogate-or-exact decision as the layer kernel; used_out[i] = 1 where the
  * surrogate answered.
@@ -251,9 +255,9 @@ ara_status ara_surrogate_calibrate(ara_ctx *ctx, int64_t n_val, uint32_t seed, d
 ara_status ara_surrogate_grad(ara_ctx *ctx, const float *tuples, int32_t n, float *grad_out, double *loss_out);
 ara_status ara_surrogate_tuples(ara_ctx *ctx, int64_t n, uint32_t seed, float *out);
 ara_status ara_surrogate_export(ara_ctx *ctx, float *params, float *adam_m, float *adam_v, int64_t *step,
-                                uint8_t *mask);
+                                uint8_t *mask, float *cell_bias);
 ara_status ara_surrogate_import(ara_ctx *ctx, const float *params, const float *adam_m, const float *adam_v,
-                                int64_t step, const uint8_t *mask);
+                                int64_t step, const uint8_t *mask, const float *cell_bias);
 ara_status ara_surrogate_eval(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                               double *x_out, int32_t *used_out);
 

@@ -83,8 +83,8 @@ def lib() -> C.CDLL:
             "ara_surrogate_calibrate": (i32, [vp, i64, u32, d, vp, vp, vp]),
             "ara_surrogate_grad": (i32, [vp, vp, i32, vp, vp]),
             "ara_surrogate_tuples": (i32, [vp, i64, u32, vp]),
-            "ara_surrogate_export": (i32, [vp, vp, vp, vp, vp, vp]),
-            "ara_surrogate_import": (i32, [vp, vp, vp, vp, i64, vp]),
+            "ara_surrogate_export": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+            "ara_surrogate_import": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_surrogate_eval": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_last_kernel_ms": (i32, [vp, C.POINTER(C.c_double)]),
             "ara_beta_quantile": (i32, [vp, vp, vp, vp, i64, vp, vp]),
@@ -336,19 +336,22 @@ def ara_surrogate_export(ctx):
     v = np.zeros(SUR_PARAMS, dtype=np.float32)
     step = C.c_int64()
     mask = np.zeros(SUR_CELLS, dtype=np.uint8)
+    bias = np.zeros(SUR_CELLS, dtype=np.float32)
     _check(ctx, lib().ara_surrogate_export(ctx, P.ctypes.data, m.ctypes.data, v.ctypes.data, C.byref(step),
-                                           mask.ctypes.data))
-    return {"params": P, "adam_m": m, "adam_v": v, "step": step.value, "mask": mask}
+                                           mask.ctypes.data, bias.ctypes.data))
+    return {"params": P, "adam_m": m, "adam_v": v, "step": step.value, "mask": mask, "bias": bias}
 
 
-def ara_surrogate_import(ctx, params, adam_m=None, adam_v=None, step: int = 1, mask=None):
+def ara_surrogate_import(ctx, params, adam_m=None, adam_v=None, step: int = 1, mask=None, bias=None):
     P = np.ascontiguousarray(params, dtype=np.float32)
     m = None if adam_m is None else np.ascontiguousarray(adam_m, dtype=np.float32)
     v = None if adam_v is None else np.ascontiguousarray(adam_v, dtype=np.float32)
     k = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    bb = None if bias is None else np.ascontiguousarray(bias, dtype=np.float32)
     _check(ctx, lib().ara_surrogate_import(ctx, P.ctypes.data, None if m is None else m.ctypes.data,
                                            None if v is None else v.ctypes.data, int(step),
-                                           None if k is None else k.ctypes.data))
+                                           None if k is None else k.ctypes.data,
+                                           None if bb is None else bb.ctypes.data))
 
 
 def ara_surrogate_eval(ctx, a, b, u):
@@ -362,14 +365,15 @@ def ara_surrogate_eval(ctx, a, b, u):
 
 
 def save_surrogate(ctx, path: str) -> None:
-    """Checkpoint the surrogate (weights, Adam state, fallback mask) as .npz."""
+    """Checkpoint the surrogate (weights, Adam state, region table) as .npz."""
     st = ara_surrogate_export(ctx)
     np.savez(path, **{k: np.asarray(v) for k, v in st.items()})
 
 
 def load_surrogate(ctx, path: str) -> None:
     with np.load(path, allow_pickle=False) as z:
-        ara_surrogate_import(ctx, z["params"], z["adam_m"], z["adam_v"], int(z["step"]), z["mask"])
+        ara_surrogate_import(ctx, z["params"], z["adam_m"], z["adam_v"], int(z["step"]), z["mask"],
+                             z["bias"] if "bias" in z.files else None)
 
 
 def ara_philox_uniforms(ctx, ctr, key0: int, key1: int, out=None, stream=None):

@@ -87,7 +87,7 @@ struct ara_ctx {
     bool sur_ready = false;
     bool sur_init = false;
     int64_t sur_step = 0;
-    DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_loss;
+    DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_bias, sur_loss;
     DevBuf sur_tuples, sur_gpart, sur_lpart, sur_calib;
     int32_t wpb[3] = {4, 4, 4};     // trial tile (wavefronts per workgroup) per mode
     bool profiling = false;
@@ -334,7 +334,8 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, const YetDev& yd, in
     (void)maxJ;
     if (mode == ARA_MODE_SURROGATE)
         HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, layers_dev, n_layers, (const MlpFrag*)c->sur_frag.p,
-                                          (const uint32_t*)c->sur_mask.p, c->wpb[mode], s));
+                                          (const uint32_t*)c->sur_mask.p, (const float*)c->sur_bias.p, c->wpb[mode],
+                                          s));
     else
         HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode],
                                 s));
@@ -457,11 +458,13 @@ ara_status sur_alloc(ara_ctx* c)
     const size_t pb = align256(kNumParams * 4);
     if ((st = dev_alloc(c, c->sur_P, pb)) || (st = dev_alloc(c, c->sur_m, pb)) || (st = dev_alloc(c, c->sur_v, pb)) ||
         (st = dev_alloc(c, c->sur_grad, pb)) || (st = dev_alloc(c, c->sur_frag, sizeof(MlpFrag))) ||
-        (st = dev_alloc(c, c->sur_mask, kCells / 8)) || (st = dev_alloc(c, c->sur_loss, 256)))
+        (st = dev_alloc(c, c->sur_mask, kCells / 8)) || (st = dev_alloc(c, c->sur_bias, kCells * 4)) ||
+        (st = dev_alloc(c, c->sur_loss, 256)))
         return st;
     HIPCHK(c, hipMemset(c->sur_m.p, 0, pb));
     HIPCHK(c, hipMemset(c->sur_v.p, 0, pb));
     HIPCHK(c, hipMemset(c->sur_mask.p, 0, kCells / 8));
+    HIPCHK(c, hipMemset(c->sur_bias.p, 0, kCells * 4));
     c->sur_step = 0;
     c->sur_init = true;
     return ARA_OK;
@@ -563,7 +566,7 @@ void ara_destroy(ara_ctx* c)
     dev_free(c, c->ws_out);
     dev_free(c, c->ws_sel);
     dev_free(c, c->ws_in);
-    for (DevBuf* b : {&c->sur_P, &c->sur_m, &c->sur_v, &c->sur_grad, &c->sur_frag, &c->sur_mask, &c->sur_loss,
+    for (DevBuf* b : {&c->sur_P, &c->sur_m, &c->sur_v, &c->sur_grad, &c->sur_frag, &c->sur_mask, &c->sur_bias, &c->sur_loss,
                       &c->sur_tuples, &c->sur_gpart, &c->sur_lpart, &c->sur_calib})
         dev_free(c, *b);
     for (auto& sl : c->stage) {
@@ -1103,6 +1106,9 @@ ara_status ara_surrogate_train(ara_ctx* c, int64_t n, int32_t epochs, int32_t ba
         }
     }
     HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
+    // the region table described the old weights
+    HIPCHK(c, hipMemset(c->sur_mask.p, 0, kCells / 8));
+    HIPCHK(c, hipMemset(c->sur_bias.p, 0, kCells * 4));
     HIPCHK(c, hipDeviceSynchronize());
     c->sur_ready = true;
     return end_call(c, nullptr);
@@ -1122,15 +1128,24 @@ ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, dou
     unsigned int* cnt = (unsigned int*)c->sur_calib.p;
     double* sum = (double*)((char*)c->sur_calib.p + kCells * 4);
     unsigned int* mx = (unsigned int*)((char*)c->sur_calib.p + kCells * 12);
-    HIPCHK(c, hipMemset(c->sur_calib.p, 0, cb));
     HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
-    HIPCHK(c, sur_launch_calib((const float*)c->sur_tuples.p, n_val, (const MlpFrag*)c->sur_frag.p, cnt, sum, mx,
-                               nullptr));
     std::vector<unsigned int> hc(kCells), hm(kCells);
     std::vector<double> hs(kCells);
-    HIPCHK(c, hipMemcpy(hc.data(), cnt, kCells * 4, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(hs.data(), sum, kCells * 8, hipMemcpyDeviceToHost));
-    HIPCHK(c, hipMemcpy(hm.data(), mx, kCells * 4, hipMemcpyDeviceToHost));
+    std::vector<float> bias(kCells, 0.0f);
+    // pass 1: each region's mean error; pass 2: the largest error left after
+    // subtracting it (the bias the layer kernel applies)
+    for (int pass = 0; pass < 2; ++pass) {
+        HIPCHK(c, hipMemset(c->sur_calib.p, 0, cb));
+        HIPCHK(c, sur_launch_calib((const float*)c->sur_tuples.p, n_val, (const MlpFrag*)c->sur_frag.p,
+                                   pass ? (const float*)c->sur_bias.p : nullptr, cnt, sum, mx, nullptr));
+        HIPCHK(c, hipMemcpy(hc.data(), cnt, kCells * 4, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hs.data(), sum, kCells * 8, hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(hm.data(), mx, kCells * 4, hipMemcpyDeviceToHost));
+        if (pass == 0) {
+            for (int i = 0; i < kCells; ++i) bias[i] = hc[i] ? (float)(hs[i] / hc[i]) : 0.0f;
+            HIPCHK(c, hipMemcpy(c->sur_bias.p, bias.data(), kCells * 4, hipMemcpyHostToDevice));
+        }
+    }
     std::vector<uint32_t> bits(kCells / 32, 0u);
     int marked = 0;
     for (int i = 0; i < kCells; ++i) {
@@ -1142,7 +1157,7 @@ ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, dou
             ++marked;
         }
         if (cell_max) cell_max[i] = hc[i] ? m : -1.0f;
-        if (cell_bias) cell_bias[i] = hc[i] ? (float)(hs[i] / hc[i]) : 0.0f;
+        if (cell_bias) cell_bias[i] = bias[i];
     }
     HIPCHK(c, hipMemcpy(c->sur_mask.p, bits.data(), kCells / 8, hipMemcpyHostToDevice));
     if (n_marked) *n_marked = marked;
@@ -1184,7 +1199,8 @@ ara_status ara_surrogate_tuples(ara_ctx* c, int64_t n, uint32_t seed, float* out
     return end_call(c, nullptr);
 }
 
-ara_status ara_surrogate_export(ara_ctx* c, float* params, float* am, float* av, int64_t* step, uint8_t* mask)
+ara_status ara_surrogate_export(ara_ctx* c, float* params, float* am, float* av, int64_t* step, uint8_t* mask,
+                                float* cell_bias)
 {
     if (!c) return ARA_E_STATE;
     if (!c->sur_init) return fail(c, ARA_E_STATE, "no surrogate to export");
@@ -1200,16 +1216,21 @@ ara_status ara_surrogate_export(ara_ctx* c, float* params, float* am, float* av,
         HIPCHK(c, hipMemcpy(bits.data(), c->sur_mask.p, kCells / 8, hipMemcpyDeviceToHost));
         for (int i = 0; i < kCells; ++i) mask[i] = (uint8_t)((bits[i >> 5] >> (i & 31)) & 1u);
     }
+    if (cell_bias) HIPCHK(c, hipMemcpy(cell_bias, c->sur_bias.p, kCells * 4, hipMemcpyDeviceToHost));
     return ARA_OK;
 }
 
 ara_status ara_surrogate_import(ara_ctx* c, const float* params, const float* am, const float* av, int64_t step,
-                                const uint8_t* mask)
+                                const uint8_t* mask, const float* cell_bias)
 {
     if (!c) return ARA_E_STATE;
     if (!params) return fail(c, ARA_E_INVAL, "params is NULL");
     for (int i = 0; i < kNumParams; ++i)
         if (!std::isfinite(params[i])) return fail(c, ARA_E_INVAL, "non-finite parameter %d", i);
+    if (cell_bias)
+        for (int i = 0; i < kCells; ++i)
+            if (!std::isfinite(cell_bias[i]) || std::fabs(cell_bias[i]) > 1.0f)
+                return fail(c, ARA_E_INVAL, "bad region bias %d", i);
     ara_status st = begin_call(c, nullptr);
     if (st) return st;
     if ((st = sur_alloc(c))) return st;
@@ -1223,6 +1244,8 @@ ara_status ara_surrogate_import(ara_ctx* c, const float* params, const float* am
         for (int i = 0; i < kCells; ++i)
             if (mask[i]) bits[i >> 5] |= 1u << (i & 31);
     HIPCHK(c, hipMemcpy(c->sur_mask.p, bits.data(), kCells / 8, hipMemcpyHostToDevice));
+    if (cell_bias) HIPCHK(c, hipMemcpy(c->sur_bias.p, cell_bias, kCells * 4, hipMemcpyHostToDevice));
+    else HIPCHK(c, hipMemset(c->sur_bias.p, 0, kCells * 4));
     HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
     HIPCHK(c, hipDeviceSynchronize());
     c->sur_ready = true;
@@ -1247,7 +1270,8 @@ ara_status ara_surrogate_eval(ara_ctx* c, const double* a, const double* b, cons
     HIPCHK(c, hipMemcpy(q + nb, b, (size_t)n * 8, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(q + 2 * nb, u, (size_t)n * 8, hipMemcpyHostToDevice));
     HIPCHK(c, sur_launch_eval((const double*)q, (const double*)(q + nb), (const double*)(q + 2 * nb), n,
-                              (const MlpFrag*)c->sur_frag.p, (const uint32_t*)c->sur_mask.p, (double*)(q + 3 * nb),
+                              (const MlpFrag*)c->sur_frag.p, (const uint32_t*)c->sur_mask.p,
+                              (const float*)c->sur_bias.p, (double*)(q + 3 * nb),
                               (int32_t*)(q + 4 * nb), nullptr));
     HIPCHK(c, hipMemcpy(x, q + 3 * nb, (size_t)n * 8, hipMemcpyDeviceToHost));
     if (used) HIPCHK(c, hipMemcpy(used, q + 4 * nb, (size_t)n * 4, hipMemcpyDeviceToHost));

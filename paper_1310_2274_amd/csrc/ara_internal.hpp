@@ -68,7 +68,8 @@ hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, i
 // ---- surrogate (ara_surrogate.hip) ----
 hipError_t launch_sur_entries(const EntryRec* pent, int64_t n, SurEntry* psur, hipStream_t s);
 hipError_t launch_layers_surrogate(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, int32_t wpb,
+                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask,
+                                   const float* bias, int32_t wpb,
                                    hipStream_t s);
 
 hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, uint32_t k1, float* out, hipStream_t s);

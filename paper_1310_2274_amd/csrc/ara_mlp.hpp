@@ -254,6 +254,12 @@ __device__ inline float mlp_forward64(const MlpFrag& F, float f0, float f1, floa
 }
 
 // Surrogate quantile for one draw (all 64 lanes must call it together).
+// Subtract a region's calibrated mean error, keeping x inside [0, 1].
+__host__ __device__ inline float sur_debias(float x, float bias)
+{
+    return fminf(fmaxf(x - bias, 0.0f), 1.0f);
+}
+
 __device__ inline float sur_quantile64(const MlpFrag& F, const SurEntry& S, float v)
 {
     const float o = mlp_forward64(F, S.f0, S.f1, v * (1.0f / 3.0f));

@@ -291,8 +291,9 @@ __device__ inline void copy_frag_to_lds(const MlpFrag* __restrict__ Fg, MlpFrag&
 }
 
 __global__ __launch_bounds__(256) void k_sur_calib(const float* __restrict__ tuples, int64_t n,
-                                                   const MlpFrag* __restrict__ Fg, unsigned int* __restrict__ cnt,
-                                                   double* __restrict__ sum, unsigned int* __restrict__ maxbits)
+                                                   const MlpFrag* __restrict__ Fg, const float* __restrict__ bias,
+                                                   unsigned int* __restrict__ cnt, double* __restrict__ sum,
+                                                   unsigned int* __restrict__ maxbits)
 {
     __shared__ MlpFrag F;
     copy_frag_to_lds(Fg, F);
@@ -303,9 +304,9 @@ __global__ __launch_bounds__(256) void k_sur_calib(const float* __restrict__ tup
     const float f0 = T[0], f1 = T[1], f2 = T[2], base = T[3], xt = T[4];
     const float o = mlp_forward64(F, f0, f1, f2);
     if (!ok) return;
-    const float xh = 1.0f / (1.0f + expf(-(base + o)));
-    const float e = xh - xt;
     const int c = sur_cell(f0, f1, 3.0f * f2);
+    const float xh = sur_debias(1.0f / (1.0f + expf(-(base + o))), bias ? bias[c] : 0.0f);
+    const float e = xh - xt;
     atomicAdd(&cnt[c], 1u);
     atomicAdd(&sum[c], (double)e);
     atomicMax(&maxbits[c], __float_as_uint(fabsf(e)));
@@ -316,7 +317,8 @@ __global__ __launch_bounds__(256) void k_sur_calib(const float* __restrict__ tup
 __global__ __launch_bounds__(256) void k_sur_eval(const double* __restrict__ a, const double* __restrict__ b,
                                                   const double* __restrict__ u, int64_t n,
                                                   const MlpFrag* __restrict__ Fg, const uint32_t* __restrict__ mask,
-                                                  double* __restrict__ x, int32_t* __restrict__ used)
+                                                  const float* __restrict__ bias, double* __restrict__ x,
+                                                  int32_t* __restrict__ used)
 {
     __shared__ MlpFrag F;
     copy_frag_to_lds(Fg, F);
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(256) void k_sur_eval(const double* __restrict__ a, 
     const float v = (float)normcdfinv(ui);
     const int c = sur_cell(S.f0, S.f1, v);
     const bool sur = sur_in_domain(ai, bi) && !((mask[c >> 5] >> (c & 31)) & 1u);
-    const float xs = sur_quantile64(F, S, v);
+    const float xs = sur_debias(sur_quantile64(F, S, v), bias[c]);
     if (!ok) return;
     if (sur) {
         x[i] = (double)xs;
@@ -364,12 +366,14 @@ __global__ void k_sur_entries(const EntryRec* __restrict__ pent, int64_t n, SurE
 
 // ===========================================================================
 // Layer kernel, surrogate mode.  As the plain kernel, with each drain round
-// split in three passes over the queued draws: (A) draw u, decide
+// split in passes over the queued draws: (A) draw u, decide
 // surrogate-or-exact from the entry's domain and the error table, and
-// compact the two kinds into separate lists; (B) evaluate the surrogate 64
-// draws at a time on the matrix cores; (C) run the exact inverse on the
-// rest.  Every draw's net loss lands at its queue position, so the per-event
-// sums keep the XELT order and the result stays a function of the trial.
+// compact the draws into three lists -- surrogate, exact FP32 solve, exact
+// FP32 + FP64 polish; (B) evaluate the surrogate 64 draws at a time on the
+// matrix cores and subtract the region's calibrated bias; (C) run the exact
+// inverse on the rest, each cost class in waves of its own.  Every draw's net
+// loss lands at its queue position, so the per-event sums keep the XELT order
+// and the result stays a function of the trial.
 // ===========================================================================
 constexpr int kSurRound = 8;
 constexpr int kSurQueue = 64 * kSurRound;
@@ -378,16 +382,19 @@ template <bool HAS_CORR, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t t0, int64_t t1,
                                                               const LayerDev* __restrict__ layers, int32_t n_layers,
                                                               const MlpFrag* __restrict__ Fg,
-                                                              const uint32_t* __restrict__ gmask)
+                                                              const uint32_t* __restrict__ gmask,
+                                                              const float* __restrict__ gbias)
 {
     __shared__ MlpFrag F;
     __shared__ uint32_t mask[kCells / 32];
+    __shared__ float bias[kCells];
     __shared__ uint32_t qidx[WPB][kSurQueue];
     __shared__ uint32_t qmeta[WPB][kSurQueue];
     __shared__ float qv[WPB][kSurQueue];
-    __shared__ uint16_t lst[WPB][2][kSurQueue];
+    __shared__ uint16_t lst[WPB][3][kSurQueue];
     copy_frag_to_lds(Fg, F);
     for (int w = threadIdx.x; w < kCells / 32; w += blockDim.x) mask[w] = gmask[w];
+    for (int w = threadIdx.x; w < kCells; w += blockDim.x) bias[w] = gbias[w];
     __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
@@ -398,7 +405,8 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
     uint32_t* QM = qmeta[w];
     float* QV = qv[w];
     uint16_t* LS = lst[w][0];
-    uint16_t* LF = lst[w][1];
+    uint16_t* LF = lst[w][1];        // exact, FP32 solve alone
+    uint16_t* LP = lst[w][2];        // exact, FP32 solve + FP64 polish (and degenerate entries)
     int64_t row;
     int32_t len;
     trial_range(y, trial, row, len);
@@ -432,11 +440,12 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                 }
                 wave_sync();
                 // (A) classify
-                int ns = 0, nf = 0;
+                int ns = 0, nf = 0, np = 0;
                 for (int b0 = 0; b0 < total; b0 += 64) {
                     const int q = b0 + lane;
-                    bool is_sur = false;
-                    if (q < total) {
+                    const bool in = q < total;
+                    bool is_sur = false, pol = false;
+                    if (in) {
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const SurEntry SE = L.psur[pi];
@@ -446,17 +455,23 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                             const int cell = sur_cell(SE.f0, SE.f1, v);
                             is_sur = !((mask[cell >> 5] >> (cell & 31)) & 1u);
                             QV[q] = v;
+                        } else {
+                            const EntryRec& E = L.pent[pi];
+                            pol = fmin(E.a, E.b) < kPolishShape;
                         }
                     }
-                    const uint64_t bs = __ballot(is_sur && q < total);
-                    const uint64_t bf = __ballot(!is_sur && q < total);
+                    const uint64_t bs = __ballot(in && is_sur);
+                    const uint64_t bf = __ballot(in && !is_sur && !pol);
+                    const uint64_t bp = __ballot(in && pol);
                     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                    if (q < total) {
+                    if (in) {
                         if (is_sur) LS[ns + __popcll(bs & below)] = (uint16_t)q;
+                        else if (pol) LP[np + __popcll(bp & below)] = (uint16_t)q;
                         else LF[nf + __popcll(bf & below)] = (uint16_t)q;
                     }
                     ns += __popcll(bs);
                     nf += __popcll(bf);
+                    np += __popcll(bp);
                 }
                 wave_sync();
                 // (B) surrogate, 64 draws per MLP evaluation
@@ -466,19 +481,34 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                     const int q = LS[act ? idx : b0];
                     const uint32_t pi = QI[q], meta = QM[q];
                     const SurEntry SE = L.psur[pi];
-                    const float xs = sur_quantile64(F, SE, QV[q]);
+                    const float v = QV[q];
+                    const float xs = sur_quantile64(F, SE, v);
                     if (act) {
                         const uint32_t j = meta >> 8;
-                        const float loss = L.pent[pi].maxl * xs;
+                        const float loss = L.pent[pi].maxl * sur_debias(xs, bias[sur_cell(SE.f0, SE.f1, v)]);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);
                     }
                 }
-                // (C) the exact inverse for the rest
+                // (C) the exact inverse for the rest: FP32 solve alone ...
                 for (int b0 = 0; b0 < nf; b0 += 64) {
                     const int idx = b0 + lane;
                     if (idx < nf) {
                         const int q = LF[idx];
+                        const uint32_t pi = QI[q], meta = QM[q];
+                        const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
+                        const EntryRec E = L.pent[pi];
+                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        const float loss = E.maxl * inv_beta32((float)z, E);
+                        const float4 jt = L.jt[j];
+                        QV[q] = jt.z * xl(loss, jt.x, jt.y);
+                    }
+                }
+                // ... and with the FP64 polish for small shapes and degenerate entries
+                for (int b0 = 0; b0 < np; b0 += 64) {
+                    const int idx = b0 + lane;
+                    if (idx < np) {
+                        const int q = LP[idx];
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
@@ -522,25 +552,27 @@ hipError_t launch_sur_entries(const EntryRec* pent, int64_t n, SurEntry* psur, h
 
 template <int WPB>
 static void launch_sur_wpb(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                           int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, hipStream_t s)
+                           int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, const float* bias,
+                           hipStream_t s)
 {
     const dim3 grid(grid_for(t1 - t0, WPB)), block(64 * WPB);
     if (has_corr)
-        hipLaunchKernelGGL((k_layer_surrogate<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers, frag, cellmask);
+        hipLaunchKernelGGL((k_layer_surrogate<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers, frag, cellmask,
+                           bias);
     else
         hipLaunchKernelGGL((k_layer_surrogate<false, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers, frag,
-                           cellmask);
+                           cellmask, bias);
 }
 
 hipError_t launch_layers_surrogate(bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
-                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask, int32_t wpb,
-                                   hipStream_t s)
+                                   int32_t n_layers, const MlpFrag* frag, const uint32_t* cellmask,
+                                   const float* bias, int32_t wpb, hipStream_t s)
 {
     if (t1 - t0 <= 0 || n_layers <= 0) return hipSuccess;
     switch (wpb) {
-        case 1: launch_sur_wpb<1>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
-        case 2: launch_sur_wpb<2>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
-        default: launch_sur_wpb<4>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, s); break;
+        case 1: launch_sur_wpb<1>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, bias, s); break;
+        case 2: launch_sur_wpb<2>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, bias, s); break;
+        default: launch_sur_wpb<4>(has_corr, y, t0, t1, layers, n_layers, frag, cellmask, bias, s); break;
     }
     return hipGetLastError();
 }
@@ -581,17 +613,19 @@ hipError_t sur_launch_build_frag(const float* P, MlpFrag* F, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, unsigned int* cnt, double* sum,
-                            unsigned int* maxbits, hipStream_t s)
+hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, const float* bias, unsigned int* cnt,
+                            double* sum, unsigned int* maxbits, hipStream_t s)
 {
-    if (n > 0) hipLaunchKernelGGL(k_sur_calib, dim3(grid_for(n, 256)), dim3(256), 0, s, tuples, n, F, cnt, sum, maxbits);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sur_calib, dim3(grid_for(n, 256)), dim3(256), 0, s, tuples, n, F, bias, cnt, sum, maxbits);
     return hipGetLastError();
 }
 
 hipError_t sur_launch_eval(const double* a, const double* b, const double* u, int64_t n, const MlpFrag* F,
-                           const uint32_t* mask, double* x, int32_t* used, hipStream_t s)
+                           const uint32_t* mask, const float* bias, double* x, int32_t* used, hipStream_t s)
 {
-    if (n > 0) hipLaunchKernelGGL(k_sur_eval, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, u, n, F, mask, x, used);
+    if (n > 0)
+        hipLaunchKernelGGL(k_sur_eval, dim3(grid_for(n, 256)), dim3(256), 0, s, a, b, u, n, F, mask, bias, x, used);
     return hipGetLastError();
 }
 

@@ -12,9 +12,9 @@ hipError_t sur_launch_train_step(const float* tuples, int64_t n_tuples, int64_t 
                                  int32_t batch, float* P, float* m, float* v, float* gpart, float* lpart, float* grad,
                                  float* loss_acc, float lr, int64_t step, bool update, hipStream_t s);
 hipError_t sur_launch_build_frag(const float* P, MlpFrag* F, hipStream_t s);
-hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, unsigned int* cnt, double* sum,
-                            unsigned int* maxbits, hipStream_t s);
+hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, const float* bias, unsigned int* cnt,
+                            double* sum, unsigned int* maxbits, hipStream_t s);
 hipError_t sur_launch_eval(const double* a, const double* b, const double* u, int64_t n, const MlpFrag* F,
-                           const uint32_t* mask, double* x, int32_t* used, hipStream_t s);
+                           const uint32_t* mask, const float* bias, double* x, int32_t* used, hipStream_t s);
 
 }  // namespace ara

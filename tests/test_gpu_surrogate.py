@@ -75,6 +75,9 @@ def test_train_calibrate_and_error_bounds(eng, tmp_path):
         # an empirical bound: allow a sliver of fresh points past it, none far past it
         assert np.mean(err[used == 1] > 1e-3) < 2e-3
         assert err[used == 1].max() < 5e-3
+        # the region bias is subtracted: what is left averages out
+        assert abs(np.mean((x - xo)[used == 1])) < 5e-5
+    assert np.all(np.isfinite(cbias)) and np.all(np.abs(cbias) <= 1) and np.all(cmax[cmax >= 0] >= 0)
     # outside the domain the plain inverse always answers
     x2, used2 = P.ara_surrogate_eval(eng.ctx, np.array([0.1, 60.0]), np.array([1.0, 2.0]), np.array([0.3, 0.3]))
     assert list(used2) == [0, 0]
@@ -86,7 +89,8 @@ def test_train_calibrate_and_error_bounds(eng, tmp_path):
         x3, used3 = P.ara_surrogate_eval(e2.ctx, a[:512], b[:512], u[:512])
     assert np.array_equal(x3, x[:512]) and np.array_equal(used3, used[:512])
     print(f"surrogate: final loss {losses[-1]:.3e}, marked cells {marked}/{P.SUR_CELLS}, "
-          f"surrogate share {used.mean():.3f}, max err {err[used == 1].max() if used.any() else 0:.2e}")
+          f"surrogate share {used.mean():.3f}, max err {err[used == 1].max() if used.any() else 0:.2e}, "
+          f"mean err {np.mean((x - xo)[used == 1]) if used.any() else 0:.2e}")
 
 
 def test_surrogate_layer_close_to_oracle(eng):
