@@ -167,6 +167,39 @@ struct InvBetaStats {
     int it32, it64;
 };
 
+// FP32 helpers of the solver's first stage: the hardware log2 / exp2 /
+// reciprocal (1 ulp each) in device code, the C library on the host.
+__host__ __device__ inline float f32_ln(float x)        // x > 0 and normal
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_logf(x) * 0.6931471805599453f;
+#else
+    return logf(x);
+#endif
+}
+__host__ __device__ inline float f32_exp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __expf(x);
+#else
+    return expf(x);
+#endif
+}
+__host__ __device__ inline float f32_rcp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+// ln(1 - t) for 0 <= t < 1: with w = fl(1 - t), ln(w) * t / (1 - w) corrects
+// the rounding of w (Goldberg's log1p), a few ulps without extended precision.
+__host__ __device__ inline float f32_log1m(float t, float w)
+{
+    return (w == 1.0f) ? -t : f32_ln(w) * (t * f32_rcp(1.0f - w));
+}
+
 __host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaStats* st = nullptr)
 {
     const bool lower = z <= (double)E.us;
@@ -177,26 +210,28 @@ __host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaS
 
     // ---- FP32 stage
     const float Af = (float)A, Bf = (float)B;
-    const float lnpf = logf((float)p);
-    const float ts = (Af + 1.0f) / (Af + Bf + 2.0f);
-    const float ymax = logf(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    const float lnpf = f32_ln((float)p);
+    const float rA = f32_rcp(Af);
+    const float ts = (Af + 1.0f) * f32_rcp(Af + Bf + 2.0f);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
     // the leading term and the constants are formed in FP64: for tiny A the
     // two logs cancel to O(A) and the FP32 difference would be noise
     const float c0f = (float)(-(lnB + log(A)));
     float y = (float)((log(p) + log(A) + lnB) / A);
-    y = fmaxf(fminf(y, logf(ts)), -1e30f);
+    y = fmaxf(fminf(y, f32_ln(ts)), -1e30f);
     // below these t the loss rounds to 0 (lower side, FP32 loss) or x to 1
     // (upper side, FP64): no need to iterate further
     const float yfloor = lower ? -110.0f : -40.0f;
     int it32 = 0;
     for (; it32 < 12 && y > yfloor; ++it32) {
-        const float t = expf(y);
-        const float l1t = log1pf(-t);
+        const float t = f32_exp(y);
+        const float w = 1.0f - t;
+        const float l1t = f32_log1m(t, w);
         float num, den;
         beta_cf<float>(t, Af, Bf, 2e-7f, 48, num, den);
-        const float T = num / den;
-        const float f = Af * y + Bf * l1t + c0f - logf(T) - lnpf;
-        const float dy = -f * (1.0f - t) / (Af * T);
+        const float rnum = f32_rcp(num);
+        const float f = Af * y + Bf * l1t + c0f + f32_ln(den * rnum) - lnpf;   // ln(1/T) = ln(den/num)
+        const float dy = -(f * w * den) * (rA * rnum);
         const float yn = fmaxf(fminf(y + dy, ymax), -1e30f);
         const float step = yn - y;
         y = yn;
@@ -240,57 +275,46 @@ __host__ __device__ inline bool needs_polish(const EntryRec& E)
 }
 
 // FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape):
-// the same log-space Newton iteration as inv_beta, in FP32 with the hardware
-// exp2/log2/reciprocal (1 ulp each).  ln(1 - t) uses Goldberg's correction
-// ln(w) * t / (1 - w) with w = fl(1 - t), which is accurate to a few ulps
-// without an extended-precision log1p.  The loop stops once a step moves the
-// quantile x by less than 5e-4 relative: Newton's quadratic convergence then
-// leaves a relative error of order 1e-6 in x.  Device only.
-__device__ __forceinline__ float hw_ln(float x)      // x > 0 and normal
-{
-    return __builtin_amdgcn_logf(x) * 0.6931471805599453f;
-}
-__device__ __forceinline__ float hw_rcp(float x)
-{
-    return __builtin_amdgcn_rcpf(x);
-}
-
+// the same log-space Newton iteration as inv_beta's first stage, with the
+// hardware helpers above.  The loop stops once a step moves the quantile x by
+// less than 5e-4 relative: Newton's quadratic convergence then leaves a
+// relative error of order 1e-6 in x.  Device only.
 __device__ inline float inv_beta32(float z, const EntryRec& E)
 {
     const bool lower = z <= E.us;
     const float A = (float)(lower ? E.a : E.b);
     const float B = (float)(lower ? E.b : E.a);
     const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
-    const float lnp = hw_ln(p);
-    const float rA = hw_rcp(A);
-    const float c0 = -((float)E.lnB + hw_ln(A));
-    const float ts = (A + 1.0f) * hw_rcp(A + B + 2.0f);
-    const float lts = hw_ln(ts);
-    const float ymax = hw_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    const float lnp = f32_ln(p);
+    const float rA = f32_rcp(A);
+    const float c0 = -((float)E.lnB + f32_ln(A));
+    const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
+    const float lts = f32_ln(ts);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
     // Start: ln I_t = A y + c0 + g(t) with g(t) = B ln(1-t) - ln T(t), which
     // vanishes at t = 0 and equals ln I_ts - A ln ts - c0 at ts (I_ts is
     // stored).  Taking g linear in t and evaluating it at the leading-term
     // root gives one cheap fixed-point step that brings the draws near ts,
     // where the leading term alone is worst, within one Newton step.
     float y = fminf((lnp - c0) * rA, lts);
-    const float gs = hw_ln(lower ? E.us : 1.0f - E.us) - A * lts - c0;
-    y = fminf((lnp - c0 - gs * __expf(y) * hw_rcp(ts)) * rA, lts);
+    const float gs = f32_ln(lower ? E.us : 1.0f - E.us) - A * lts - c0;
+    y = fminf((lnp - c0 - gs * __expf(y) * f32_rcp(ts)) * rA, lts);
     const float yfloor = lower ? -110.0f : -40.0f;
     for (int it = 0; it < 10 && y > yfloor; ++it) {
         const float t = __expf(y);
         const float w = 1.0f - t;
-        const float l1t = (w == 1.0f) ? -t : hw_ln(w) * (t * hw_rcp(1.0f - w));
+        const float l1t = f32_log1m(t, w);
         float num, den;
         beta_cf<float>(t, A, B, 2e-7f, 48, num, den);
-        const float rnum = hw_rcp(num);
-        const float f = A * y + B * l1t + c0 + hw_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
+        const float rnum = f32_rcp(num);
+        const float f = A * y + B * l1t + c0 + f32_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
         const float dy = -(f * w * den) * (rA * rnum);
         const float yn = fminf(y + dy, ymax);
         const float step = yn - y;
         y = yn;
         // a step dy moves x by dy (lower side, x = t) or by dy * t / (1 - t)
         // relative to x (upper side, x = 1 - t)
-        if (fabsf(step) * (lower ? 1.0f : t * hw_rcp(w)) <= 5e-4f) break;
+        if (fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
     }
     return lower ? __expf(y) : -expm1f(y);
 }
