@@ -67,7 +67,8 @@ uint64_t    ara_bytes_in_use(const ara_ctx *ctx);
  * Otherwise trial i is event_ids[trial_offsets[i] .. trial_offsets[i+1])
  * (int64 [n_trials+1], host memory, non-decreasing, starting at 0) and
  * events_per_trial is ignored.  Every id must lie in [0, catalog_size)
- * (ARA_E_RANGE otherwise).  n_trials must be below 2^32.
+ * (ARA_E_RANGE otherwise).  n_trials must be below 2^32 and no trial may
+ * hold 2^24 or more events (ARA_E_INVAL otherwise).
  */
 ara_status ara_load_yet(ara_ctx *ctx, const int32_t *event_ids, const int64_t *trial_offsets,
                         int64_t n_trials, int32_t events_per_trial, int32_t catalog_size,

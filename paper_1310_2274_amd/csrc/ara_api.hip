@@ -593,13 +593,19 @@ ara_status ara_load_yet(ara_ctx* c, const int32_t* event_ids, const int64_t* tri
     if (n_trials < 0 || n_trials >= ((int64_t)1 << 32)) return fail(c, ARA_E_INVAL, "n_trials must be in [0, 2^32)");
     if (catalog_size <= 0) return fail(c, ARA_E_INVAL, "catalog_size must be positive");
     int64_t total;
+    // the layer kernels index a trial's events with 24 bits
+    const int64_t max_len = ((int64_t)1 << 24) - 1;
     if (trial_offsets) {
         if (trial_offsets[0] != 0) return fail(c, ARA_E_INVAL, "trial_offsets[0] must be 0");
-        for (int64_t i = 0; i < n_trials; ++i)
+        for (int64_t i = 0; i < n_trials; ++i) {
             if (trial_offsets[i + 1] < trial_offsets[i]) return fail(c, ARA_E_INVAL, "trial_offsets must not decrease");
+            if (trial_offsets[i + 1] - trial_offsets[i] > max_len)
+                return fail(c, ARA_E_INVAL, "trial %lld has more than 2^24 - 1 events", (long long)i);
+        }
         total = trial_offsets[n_trials];
     } else {
-        if (events_per_trial < 0) return fail(c, ARA_E_INVAL, "events_per_trial must be >= 0");
+        if (events_per_trial < 0 || events_per_trial > max_len)
+            return fail(c, ARA_E_INVAL, "events_per_trial must be in [0, 2^24)");
         total = n_trials * (int64_t)events_per_trial;
     }
     if (total > 0 && !event_ids) return fail(c, ARA_E_INVAL, "event_ids is NULL");

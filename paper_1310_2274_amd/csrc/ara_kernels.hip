@@ -197,28 +197,47 @@ constexpr int kChunk = 64;                   // event slots per compaction round
 constexpr int kRound = 8;                    // draws per slot per drain round
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 
-// One drain round of the plain path: the queued draws are split into those
-// the FP32 solve handles alone and those that need the FP64 polish (small
-// shape parameters, degenerate entries), and each list is drained 64 draws at
-// a time so a wave's lanes share one cost class.  Each draw's net loss lands
-// at its queue position.
+// Plain path, one wave per trial.  Each chunk of 64 event slots is drained in
+// rounds: the queued draws of a round are classified by cost.  Draws whose
+// smaller shape parameter is at least kPolishShape take the FP32 solve alone
+// and are drained 64 at a time at once.  The rest (small shapes that need the
+// FP64 polish, and degenerate entries) are few -- a handful per chunk -- so
+// they go to a per-wave deferred queue that is drained only in full waves of
+// 64 (and once, partially, at the end of the trial).  An event whose draws
+// are still deferred keeps its partial loss in a small ring of pending chunks
+// and takes its occurrence terms once the last of them lands.  Every sum is a
+// fixed function of the trial, so the result does not depend on the launch.
+constexpr int kDefer = 128;                  // deferred-draw ring per wave (power of two)
+constexpr int kRing = 4;                     // chunks that may wait for deferred draws (four register sums)
+constexpr int kFinal = 1 << 30;              // pending count of a finished (or empty) slot
+constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
+
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 1 : 3))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
     __shared__ uint32_t qmeta[WPB][kQueue];
     __shared__ float qv[WPB][kQueue];
-    __shared__ uint16_t lst[WPB][2][kQueue];
+    __shared__ uint16_t lst[WPB][kQueue];
+    __shared__ uint32_t didx[WPB][kDefer];
+    __shared__ uint32_t dmeta[WPB][kDefer];
+    __shared__ float pcs[WPB][kRing][64];
+    __shared__ int pns[WPB][kRing][64];
+    __shared__ int rchunk[WPB][kRing];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
     if (trial >= t1) return;
     uint32_t* QI = qidx[w];          // packed entry index
     uint32_t* QM = qmeta[w];         // slot within chunk | XELT position << 8
-    float* QV = qv[w];               // the draw's net loss
-    uint16_t* L32 = lst[w][0];
-    uint16_t* L64 = lst[w][1];
+    float* QV = qv[w];               // the draw's net loss, or kDeferred
+    uint16_t* L32 = lst[w];
+    uint32_t* DI = didx[w];          // deferred draws: packed entry index
+    uint32_t* DM = dmeta[w];         //   slot within the trial | XELT position << 24
+    float (*PC)[64] = pcs[w];        // pending chunks: partial event loss per slot
+    int (*PN)[64] = pns[w];          //   deferred draws outstanding per slot
+    int* RC = rchunk[w];             //   chunk held by each ring slot (-1: free)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     int64_t row;
@@ -229,16 +248,95 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, 
     for (int32_t l = 0; l < n_layers; ++l) {
         const LayerDev& L = layers[l];
         float S = 0.0f, Sc = 0.0f, omax = 0.0f;
-        for (int32_t base = 0; base < len; base += kChunk) {
+        int dh = 0, dn = 0;                        // deferred ring: head, count (wave-uniform)
+        if (lane < kRing) RC[lane] = -1;
+        wave_sync();
+
+        // Occurrence terms of every settled slot of ring slot r (its chunk's
+        // rounds are over): those with no deferred draw outstanding.
+        auto settle = [&](int r) {
+            const int ci = RC[r];
+            if (ci < 0) return;
+            if (PN[r][lane] == 0) {
+                const float o = xl(PC[r][lane], L.occR, L.occL);
+                omax = fmaxf(omax, o);
+                neumaier_add(S, Sc, o);
+                PN[r][lane] = kFinal;
+            }
+            if (__ballot(PN[r][lane] != kFinal) == 0ull) RC[r] = -1;
+            wave_sync();
+        };
+        // Evaluate the m <= 64 oldest deferred draws, one per lane, then hand
+        // each value, in queue order, to the lane that owns its slot: the
+        // owner sums its values per ring slot in registers and adds each sum
+        // to the slot's partial loss.
+        auto flush = [&](int m, int open_ring) {
+            const int e = (dh + lane) & (kDefer - 1);
+            float v = 0.0f;
+            uint32_t key = 0;
+            if (lane < m) {
+                const uint32_t pi = DI[e], meta = DM[e];
+                const uint32_t j = meta >> 24;
+                key = meta & 0xFFFFFFu;
+                const EntryRec E = L.pent[pi];
+                const double z = draw_z<HAS_CORR>(tr, key, j, L.seed, L.prog, L.pcw, pi);
+                const float loss = sample_loss(z, E);
+                const float4 jt = L.jt[j];
+                v = jt.z * xl(loss, jt.x, jt.y);
+            }
+            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+            int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+            for (int i = 0; i < m; ++i) {
+                const uint32_t ki = (uint32_t)__builtin_amdgcn_readlane((int)key, i);
+                const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+                const bool own = (int)(ki & 63u) == lane;
+                const float add = own ? vi : 0.0f;
+                const int cnt = own ? 1 : 0;
+                switch ((ki >> 6) & (uint32_t)(kRing - 1)) {
+                    case 0: a0 += add; n0 += cnt; break;
+                    case 1: a1 += add; n1 += cnt; break;
+                    case 2: a2 += add; n2 += cnt; break;
+                    default: a3 += add; n3 += cnt; break;
+                }
+            }
+            PC[0][lane] += a0;
+            PN[0][lane] -= n0;
+            PC[1][lane] += a1;
+            PN[1][lane] -= n1;
+            PC[2][lane] += a2;
+            PN[2][lane] -= n2;
+            PC[3][lane] += a3;
+            PN[3][lane] -= n3;
+            dh = (dh + m) & (kDefer - 1);
+            dn -= m;
+            wave_sync();
+            for (int r = 0; r < kRing; ++r)
+                if (r != open_ring) settle(r);
+        };
+
+        for (int32_t ci = 0;; ++ci) {
+            const int32_t base = ci * kChunk;
+            const bool more = base < len;
+            const int r = ci & (kRing - 1);
+            // the ring slot must be free, and nothing may stay deferred past the trial
+            if (!more || RC[r] >= 0)
+                while (dn > 0) flush(dn < 64 ? dn : 64, -1);
+            if (!more) break;
+            PC[r][lane] = 0.0f;
+            PN[r][lane] = 0;
+            if (lane == 0) RC[r] = ci;
+            wave_sync();
+
             const int32_t k = base + lane;
             const bool valid = k < len;
-            uint4 r = make_uint4(0, 0, 0, 0);
-            if (valid) r = L.rows[y.ev[row + k]];
-            uint64_t mask = (uint64_t)r.x | ((uint64_t)r.y << 32);
-            const uint32_t off = r.z;
-            int remaining = (int)r.w;
+            uint4 rr = make_uint4(0, 0, 0, 0);
+            if (valid) rr = L.rows[y.ev[row + k]];
+            uint64_t mask = (uint64_t)rr.x | ((uint64_t)rr.y << 32);
+            const uint32_t off = rr.z;
+            int remaining = (int)rr.w;
             int rank = 0;
-            float c = 0.0f;                  // this event's loss across XELTs
+            float c = 0.0f;                  // this event's loss across XELTs, deferred draws aside
+            int pend = 0;                    // its deferred draws
             while (true) {
                 const int take = remaining < kRound ? remaining : kRound;
                 const int incl = wave_incl_scan(take);
@@ -252,8 +350,8 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, 
                     QM[pos + i] = (uint32_t)lane | ((uint32_t)j << 8);
                 }
                 wave_sync();
-                // (A) classify
-                int n32 = 0, n64 = 0;
+                // (A) classify: FP32 draws to the list, the others to the deferred ring
+                int n32 = 0;
                 for (int b0 = 0; b0 < total; b0 += 64) {
                     const int q = b0 + lane;
                     const bool in = q < total;
@@ -265,13 +363,21 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, 
                     const uint64_t b64 = __ballot(in && pol);
                     const uint64_t b32 = __ballot(in && !pol);
                     if (in) {
-                        if (pol) L64[n64 + __popcll(b64 & below)] = (uint16_t)q;
-                        else L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
+                        if (pol) {
+                            const int e = (dh + dn + __popcll(b64 & below)) & (kDefer - 1);
+                            const uint32_t meta = QM[q];
+                            DI[e] = QI[q];
+                            DM[e] = ((uint32_t)base + (meta & 63u)) | ((meta >> 8) << 24);
+                            QV[q] = kDeferred;
+                        } else {
+                            L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
+                        }
                     }
-                    n64 += __popcll(b64);
                     n32 += __popcll(b32);
+                    dn += __popcll(b64);
+                    wave_sync();
+                    if (dn >= 64) flush(64, r);
                 }
-                wave_sync();
                 // (B) FP32 solve
                 for (int b0 = 0; b0 < n32; b0 += 64) {
                     const int idx = b0 + lane;
@@ -286,31 +392,21 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, 
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
                     }
                 }
-                // (C) FP32 solve + FP64 polish, and degenerate entries
-                for (int b0 = 0; b0 < n64; b0 += 64) {
-                    const int idx = b0 + lane;
-                    if (idx < n64) {
-                        const int q = L64[idx];
-                        const uint32_t pi = QI[q], meta = QM[q];
-                        const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
-                        const EntryRec E = L.pent[pi];
-                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                        const float loss = sample_loss(z, E);
-                        const float4 jt = L.jt[j];
-                        QV[q] = jt.z * xl(loss, jt.x, jt.y);
-                    }
-                }
                 wave_sync();
-                for (int i = 0; i < take; ++i) c += QV[pos + i];
+                for (int i = 0; i < take; ++i) {
+                    const float v = QV[pos + i];
+                    if (v == kDeferred) ++pend;
+                    else c += v;
+                }
                 rank += take;
                 remaining -= take;
                 wave_sync();
             }
-            if (valid) {
-                const float o = xl(c, L.occR, L.occL);                 // occurrence terms
-                omax = fmaxf(omax, o);
-                neumaier_add(S, Sc, o);
-            }
+            // the chunk's rounds are over: slots with nothing deferred settle now
+            PC[r][lane] += c;
+            PN[r][lane] = valid ? PN[r][lane] + pend : kFinal;
+            wave_sync();
+            settle(r);
         }
         wave_sum_pair(S, Sc);
         omax = wave_max(omax);
@@ -319,6 +415,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_plain(YetDev y, int64_t t0, 
             L.ylt[trial - t0] = Y;
             if (L.omax) L.omax[trial - t0] = omax;
         }
+        wave_sync();
     }
 }
 
