@@ -37,11 +37,11 @@ PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 PEAK_VALU_TOPS = 157.3 / 2
 # VALU lane-instructions per draw of the plain layer kernel on this workload,
 # SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 1787.1
+VALU_OPS_PER_DRAW = 1529.6
 # Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2 * 17441621.0 + 2027.4) * 1024
+TRAFFIC_BYTES = 8 * (2.0 * 19585239.8 + 3037.7) * 1024
 
 
 def log(msg):
@@ -76,6 +76,18 @@ def cpu_baseline(wl, seconds: float, threads: int):
             "kind": "oracle",
             "sample": f"trials 0..{done - 1} of the {wl.n_trials}-trial YET ({done * wl.events_per_trial} "
                       f"trial-events, {t_used:.1f} s, FP64 C oracle, OpenMP over trials)"}
+
+
+def autotune(P, eng, yh, desc, mode, n_trials):
+    """Pick the trial tile (wavefronts per workgroup) for this layer and mode on
+    a slice of the YET, outside the timed region."""
+    h = P.ara_prepare_layer(eng.ctx, desc, mode)
+    try:
+        best, ms = P.ara_autotune(eng.ctx, yh, [h], n_trials)
+    finally:
+        P.ara_free_layer(eng.ctx, h)
+    return {"waves_per_workgroup": int(best), "candidates": [1, 2, 4, 8],
+            "slice_ms": [None if not np.isfinite(m) else round(float(m), 3) for m in ms], "slice_trials": n_trials}
 
 
 def timed_steps(P, torch, eng, yh, desc, mode, seed, out, rps, steps, warmup):
@@ -205,6 +217,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default trial tile (4 waves per workgroup)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (FETCH_SIZE/WRITE_SIZE calibration under rocprofv3)")
     args = ap.parse_args()
@@ -238,6 +251,11 @@ def main():
     rps = P.DEFAULT_RETURN_PERIODS
     log(f"setup {time.perf_counter() - t_setup:.1f} s, {draws} draws/pass")
 
+    tune = {}
+    if not args.no_autotune:
+        tune["plain"] = autotune(P, eng, yh, desc, P.MODE_PLAIN, min(N, 100_000))
+        log(f"trial tile (plain): {tune['plain']['waves_per_workgroup']} waves/workgroup, "
+            f"slice ms {tune['plain']['slice_ms']}")
     step_s, kernel_ms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps,
                                                args.steps, args.warmup)
     value = N * K / step_s
@@ -250,6 +268,8 @@ def main():
 
     mean_leg = None
     if not args.no_mean_leg:
+        if not args.no_autotune:
+            tune["mean"] = autotune(P, eng, yh, desc, P.MODE_MEAN, min(N, 200_000))
         mstep, mk, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_MEAN, wl.seed, out, rps, max(3, args.steps), 2)
         gbs = (N * K * 4 + N * 4) / (mk * 1e-3) / 1e9
         mean_leg = {"bound": "hbm", "kernel": "k_layer_mean", "kernel_ms": mk, "achieved": gbs,
@@ -287,6 +307,7 @@ def main():
                    "n_trials": N, "events_per_trial": K, "n_elts": len(lay.elts), "draws_per_step": draws},
         "roofline": roof,
         "roofline_streaming": mean_leg,
+        "trial_tile": tune or None,
         "surrogate": sur,
         "portfolio": port,
         "serving": serve,
