@@ -168,7 +168,9 @@ ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *lay
  * choice on the first n_trials trials for the given prepared layers (all of
  * one mode), keeps the fastest for that mode and returns it (ms_out,
  * optional: the time of each candidate 1, 2, 4, 8, float [4]).  Results do not
- * depend on the choice.
+ * depend on the choice.  The mean mode has a fixed launch shape (catalog
+ * slices of the per-event table in LDS, 16 wavefronts per workgroup) and
+ * ignores the tile.
  */
 ara_status ara_set_trial_tile(ara_ctx *ctx, ara_mode mode, int32_t wpb);
 ara_status ara_autotune(ara_ctx *ctx, int32_t yet_handle, const int32_t *layer_handles, int32_t n_layers,

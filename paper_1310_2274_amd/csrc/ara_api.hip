@@ -29,7 +29,9 @@ struct DevBuf {
 struct YetRec {
     bool live = false;
     DevBuf ev, offs;
-    int64_t N = 0;
+    DevBuf sev, sseg;     // mean mode: slice-major copy of the ids and its group offsets (built on first use)
+    bool sliced = false;
+    int64_t N = 0, total = 0;
     int32_t K = 0, C = 0;
 };
 
@@ -77,6 +79,7 @@ struct ara_ctx {
     DevBuf ws_out;        // device staging for host outputs
     DevBuf ws_sel;        // risk-measure state
     DevBuf ws_in;         // device staging for host inputs
+    DevBuf ws_mean;       // mean mode: per-slice partial sums
     double* sel_host = nullptr;
     StageSlot stage[kStageSlots];
     int next_stage = 0;
@@ -327,18 +330,42 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     return ARA_OK;
 }
 
-ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, const YetDev& yd, int64_t t0, int64_t t1,
+// Mean mode reads a slice-major copy of the YET, built once per YET.
+ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
+{
+    const int32_t ns = mean_slices(y.C);
+    if (ns == 0 || y.sliced) return ARA_OK;
+    ara_status st;
+    const size_t ints = (size_t)y.total + (size_t)4 * (ns + 1) * (size_t)y.N + 4;
+    if ((st = dev_alloc(c, y.sev, ints * 4))) return st;
+    if ((st = dev_alloc(c, y.sseg, (size_t)y.N * (ns + 1) * 4 + 4))) {
+        dev_free(c, y.sev);
+        return st;
+    }
+    HIPCHK(c, launch_yet_slice(yd, (int32_t*)y.sev.p, (int32_t*)y.sseg.p, s));
+    y.sliced = true;
+    return ARA_OK;
+}
+
+ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const YetDev& yd, int64_t t0, int64_t t1,
                        const LayerDev* layers_dev, int32_t n_layers, int32_t maxJ, hipStream_t s)
 {
+    if (mode == ARA_MODE_MEAN) {
+        ara_status st = ws_reserve(c, c->ws_mean, mean_workspace_bytes(yd.C, t1 - t0));
+        if (st) return st;
+        if ((st = ensure_sliced(c, yr, yd, s))) return st;
+    }
     if (c->profiling) HIPCHK(c, hipEventRecord(c->k_start, s));
     (void)maxJ;
     if (mode == ARA_MODE_SURROGATE)
         HIPCHK(c, launch_layers_surrogate(has_corr, yd, t0, t1, layers_dev, n_layers, (const MlpFrag*)c->sur_frag.p,
                                           (const uint32_t*)c->sur_mask.p, (const float*)c->sur_bias.p, c->wpb[mode],
                                           s));
+    else if (mode == ARA_MODE_MEAN)
+        HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const int32_t*)yr.sseg.p,
+                              c->ws_mean.p, s));
     else
-        HIPCHK(c, launch_layers(mode == ARA_MODE_MEAN ? 0 : 1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode],
-                                s));
+        HIPCHK(c, launch_layers(1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(c->k_stop, s));
         c->have_timing = true;
@@ -358,7 +385,7 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live)
         return fail(c, ARA_E_STATE, "unknown YET handle %d", yh);
     if (n_layers < 1 || !layers || !ylt_outs) return fail(c, ARA_E_INVAL, "no layers or outputs");
-    const YetRec& y = c->yets[yh];
+    YetRec& y = c->yets[yh];
     if (t0 < 0 || t1 > y.N || t0 > t1) return fail(c, ARA_E_RANGE, "trial range [%lld, %lld) outside [0, %lld)",
                                                    (long long)t0, (long long)t1, (long long)y.N);
     hipStream_t s = pick_stream(c, hip_stream);
@@ -430,7 +457,7 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     StageSlot* sl2 = nullptr;
     if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl2))) return st;
     YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
-    if ((st = launch_mode(c, mode, has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, maxJ, s))) return st;
+    if ((st = launch_mode(c, mode, has_corr, y, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, maxJ, s))) return st;
     if ((st = release_stage(c, sl1, s))) return st;
     if ((st = release_stage(c, sl2, s))) return st;
     bool sync = false;
@@ -566,6 +593,7 @@ void ara_destroy(ara_ctx* c)
     dev_free(c, c->ws_out);
     dev_free(c, c->ws_sel);
     dev_free(c, c->ws_in);
+    dev_free(c, c->ws_mean);
     for (DevBuf* b : {&c->sur_P, &c->sur_m, &c->sur_v, &c->sur_grad, &c->sur_frag, &c->sur_mask, &c->sur_bias, &c->sur_loss,
                       &c->sur_tuples, &c->sur_gpart, &c->sur_lpart, &c->sur_calib})
         dev_free(c, *b);
@@ -613,6 +641,7 @@ ara_status ara_load_yet(ara_ctx* c, const int32_t* event_ids, const int64_t* tri
     if (st) return st;
     YetRec y;
     y.N = n_trials;
+    y.total = total;
     y.K = trial_offsets ? 0 : events_per_trial;
     y.C = catalog_size;
     if ((st = dev_alloc(c, y.ev, (size_t)total * 4))) return st;
@@ -654,6 +683,9 @@ ara_status ara_free_yet(ara_ctx* c, int32_t h)
     HIPCHK(c, hipDeviceSynchronize());
     dev_free(c, c->yets[h].ev);
     dev_free(c, c->yets[h].offs);
+    dev_free(c, c->yets[h].sev);
+    dev_free(c, c->yets[h].sseg);
+    c->yets[h].sliced = false;
     c->yets[h].live = false;
     return ARA_OK;
 }
@@ -843,7 +875,7 @@ ara_status ara_run_prepared(ara_ctx* c, int32_t yh, const int32_t* handles, int3
     if (!c) return ARA_E_STATE;
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
     if (n < 1 || !handles || !seeds || !ylt_outs) return fail(c, ARA_E_INVAL, "bad arguments to ara_run_prepared");
-    const YetRec& y = c->yets[yh];
+    YetRec& y = c->yets[yh];
     if (t0 < 0 || t1 > y.N || t0 > t1) return fail(c, ARA_E_RANGE, "trial range outside the YET");
     std::vector<LayerDev> devs((size_t)n);
     int mode = -1;
@@ -874,7 +906,7 @@ ara_status ara_run_prepared(ara_ctx* c, int32_t yh, const int32_t* handles, int3
     StageSlot* sl = nullptr;
     if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl))) return st;
     YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
-    if ((st = launch_mode(c, mode, has_corr, yd, t0, t1, (const LayerDev*)layers_dev, n, maxJ, s))) return st;
+    if ((st = launch_mode(c, mode, has_corr, y, yd, t0, t1, (const LayerDev*)layers_dev, n, maxJ, s))) return st;
     if ((st = release_stage(c, sl, s))) return st;
     return end_call(c, s);
 }

@@ -62,6 +62,16 @@ hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uin
 hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,
                              float* occ_tab, hipStream_t s);
 // wpb: wavefronts (= trials) per workgroup, 1, 2, 4 or 8 -- the trial tile
+// Mean mode: catalog slices of the per-event table in LDS over a slice-major
+// copy of the YET (mean_slices() == 0: too many slices, the table is read
+// through L2 instead).  The copy of a YET with N trials and T ids holds
+// T + 4 * (ns + 1) * N + 4 ints and N * (ns + 1) group offsets; the
+// workspace holds each slice's per-trial partial sums and maxima.
+int32_t mean_slices(int32_t C);
+size_t mean_workspace_bytes(int32_t C, int64_t n_trials);
+hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStream_t s);
+hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
+                       const int32_t* ev2, const int32_t* seg, void* ws, hipStream_t s);
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
                          const LayerDev* layers, int32_t n_layers, int32_t wpb, hipStream_t s);
 

@@ -419,44 +419,205 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     }
 }
 
-// Mean mode: stream the event ids (16-byte loads when the rows allow it) and
-// gather the tabulated occurrence loss; HBM-bound.
-template <int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_layer_mean(YetDev y, int64_t t0, int64_t t1,
-                                                         const LayerDev* __restrict__ layers, int32_t n_layers)
+// Mean mode (the streaming phase): the per-event loss net of XELT and
+// occurrence terms is tabulated per event (k_mean_table), so a trial's year
+// loss is the sum of one table value per event.  Gathering those values from
+// L2 caps the rate at the L2 request rate, far below HBM.  Instead the
+// catalog is cut into slices of 72 KB of LDS (two workgroups of 16
+// wavefronts fill a CU's 160 KB and its 32 wavefront slots), and the YET
+// gets a slice-major copy (once per YET, k_yet_slice): each trial's ids
+// regrouped by slice, each group padded with -1 to a multiple of four.
+// Workgroup (tile, slice) holds its slice of the table in LDS and streams
+// only that slice's ids of its trials, so every id is read once.
+// k_mean_finish adds a trial's slice sums in slice order (FP64) and applies
+// the aggregate terms.  Catalogs of more than kMaxSlices slices use
+// k_mean_gather, which reads the table through L2.
+constexpr int kSliceMax = 18432;             // table entries per slice (72 KB of LDS: two workgroups per CU)
+constexpr int kMaxSlices = 16;
+constexpr int kMeanWaves = 16;               // wavefronts per workgroup
+constexpr int kMeanTile = 1024;              // trials per workgroup
+constexpr int kLanesPerTrial = 16;           // lanes streaming one trial's group
+constexpr int kTrialsPerWave = 64 / kLanesPerTrial;
+
+// Start of trial t's regrouped ids: 16-byte aligned, with room for the
+// padding of every group.
+__device__ __forceinline__ int64_t sliced_base(int64_t row, int64_t t, int32_t ns)
 {
+    return ((row + 3) & ~(int64_t)3) + 4 * (int64_t)(ns + 1) * t;
+}
+
+__global__ __launch_bounds__(256) void k_yet_slice(YetDev y, int32_t slice_len, int32_t ns, int32_t* __restrict__ ev2,
+                                                   int32_t* __restrict__ seg)
+{
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= y.N) return;
+    const int lane = lane_id();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t row;
+    int32_t len;
+    trial_range(y, t, row, len);
+    const int64_t base = sliced_base(row, t, ns);
+    int32_t* sg = seg + t * (int64_t)(ns + 1);
+    // group sizes, padded to multiples of four, and their starts
+    int32_t st[kMaxSlices];
+    int32_t start = 0;
+#pragma unroll
+    for (int32_t sl = 0; sl < kMaxSlices; ++sl) {
+        st[sl] = start;
+        if (sl < ns) {
+            int32_t cnt = 0;
+            for (int32_t k0 = 0; k0 < len; k0 += 64) {
+                const int32_t k = k0 + lane;
+                const bool in = k < len && y.ev[row + k] / slice_len == sl;
+                cnt += __popcll(__ballot(in));
+            }
+            if (lane == 0) sg[sl] = start;
+            const int32_t padded = (cnt + 3) & ~3;
+            for (int32_t q = cnt + lane; q < padded; q += 64) ev2[base + start + q] = -1;
+            start += padded;
+        }
+    }
+    if (lane == 0) sg[ns] = start;
+    // scatter, keeping the time order inside each group
+    int32_t fill[kMaxSlices];
+#pragma unroll
+    for (int32_t sl = 0; sl < kMaxSlices; ++sl) fill[sl] = 0;
+    for (int32_t k0 = 0; k0 < len; k0 += 64) {
+        const int32_t k = k0 + lane;
+        const int32_t id = k < len ? y.ev[row + k] : 0;
+        const int32_t mine = k < len ? id / slice_len : -1;
+#pragma unroll
+        for (int32_t sl = 0; sl < kMaxSlices; ++sl) {
+            if (sl < ns) {
+                const uint64_t m = __ballot(mine == sl);
+                if (mine == sl) ev2[base + st[sl] + fill[sl] + __popcll(m & below)] = id;
+                fill[sl] += __popcll(m);
+            }
+        }
+    }
+}
+
+// kLanesPerTrial lanes per trial, kTrialsPerWave trials per wavefront at a
+// time, so each wavefront keeps several 16-byte loads of several trials in
+// flight; the next trials' group offsets are fetched one iteration ahead.
+__global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_t t0, int64_t t1,
+                                                                 const LayerDev* __restrict__ layers, int32_t l,
+                                                                 const int32_t* __restrict__ ev2,
+                                                                 const int32_t* __restrict__ seg, int32_t slice_len,
+                                                                 int32_t ns, float2* __restrict__ part,
+                                                                 float* __restrict__ pmax)
+{
+    __shared__ float4 stab4[kSliceMax / 4];
+    const float* stab = reinterpret_cast<const float*>(stab4);
+    const int64_t tile = blockIdx.x / ns;
+    const int32_t sl = (int32_t)(blockIdx.x % ns);
+    const LayerDev& L = layers[l];
+    const int32_t lo = sl * slice_len;                   // slice_len is a multiple of 4
+    const int32_t n = min(slice_len, y.C - lo);
+    const float4* src4 = reinterpret_cast<const float4*>(L.occ_tab + lo);
+    for (int i = threadIdx.x; i < (n >> 2); i += blockDim.x) stab4[i] = src4[i];
+    for (int i = (n & ~3) + threadIdx.x; i < n; i += blockDim.x) reinterpret_cast<float*>(stab4)[i] = L.occ_tab[lo + i];
+    __syncthreads();
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
-    const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
+    const int grp = lane / kLanesPerTrial, sub = lane % kLanesPerTrial;
+    const uint32_t un = (uint32_t)n;
+    const int64_t nt = t1 - t0;
+    const int64_t tb = tile * kMeanTile;
+    const int64_t te = min(nt, tb + (int64_t)kMeanTile);
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    // where trial i's group for this slice lives: offset into the copy, length in int4
+    auto locate = [&](int64_t i, int64_t& at, int32_t& n4) {
+        at = 0;
+        n4 = 0;
+        if (i < te) {
+            const int64_t t = t0 + i;
+            const int64_t row = y.offs ? y.offs[t] : t * (int64_t)y.K;
+            const int32_t* sg = seg + t * (int64_t)(ns + 1);
+            const int32_t a = sg[sl], b = sg[sl + 1];
+            at = sliced_base(row, t, ns) + a;
+            n4 = (b - a) >> 2;
+        }
+    };
+    int64_t at_next;
+    int32_t n4_next;
+    locate(tb + kTrialsPerWave * w + grp, at_next, n4_next);
+    for (int64_t i0 = tb + kTrialsPerWave * w; i0 < te; i0 += kTrialsPerWave * kMeanWaves) {
+        const int64_t i = i0 + grp;
+        const bool live = i < te;
+        const int64_t at = at_next;
+        const int32_t n4 = n4_next;
+        locate(i + kTrialsPerWave * kMeanWaves, at_next, n4_next);   // the next group's offsets, in flight early
+        const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(ev2 + at);
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, m = 0.0f;
+#pragma unroll 4
+        for (int32_t q = sub; q < n4; q += kLanesPerTrial) {
+            const v4i e = __builtin_nontemporal_load(v4 + q);
+            const uint32_t u0 = (uint32_t)(e.x - lo), u1 = (uint32_t)(e.y - lo);
+            const uint32_t u2 = (uint32_t)(e.z - lo), u3 = (uint32_t)(e.w - lo);
+            const float v0 = u0 < un ? stab[u0] : 0.0f;          // -1 padding falls outside
+            const float v1 = u1 < un ? stab[u1] : 0.0f;
+            const float v2 = u2 < un ? stab[u2] : 0.0f;
+            const float v3 = u3 < un ? stab[u3] : 0.0f;
+            a0 += v0;
+            a1 += v1;
+            a2 += v2;
+            a3 += v3;
+            m = fmaxf(m, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
+        }
+        float S = a0, Sc = 0.0f;
+        neumaier_add(S, Sc, a1);
+        neumaier_add(S, Sc, a2);
+        neumaier_add(S, Sc, a3);
+#pragma unroll
+        for (int k = kLanesPerTrial / 2; k >= 1; k >>= 1) {   // within the trial's lanes
+            const float oh = __shfl_xor(S, k, kLanesPerTrial);
+            const float ol = __shfl_xor(Sc, k, kLanesPerTrial);
+            two_sum_merge(S, Sc, oh, ol);
+            m = fmaxf(m, __shfl_xor(m, k, kLanesPerTrial));
+        }
+        if (live && sub == 0) {
+            part[(int64_t)sl * nt + i] = make_float2(S, Sc);
+            pmax[(int64_t)sl * nt + i] = m;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mean_finish(const LayerDev* __restrict__ layers, int32_t l, int64_t nt,
+                                                     int32_t ns, const float2* __restrict__ part,
+                                                     const float* __restrict__ pmax)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    const LayerDev& L = layers[l];
+    double S = 0.0;
+    float m = 0.0f;
+    for (int32_t sl = 0; sl < ns; ++sl) {
+        const float2 p = part[(int64_t)sl * nt + i];
+        S += (double)p.x + (double)p.y;
+        m = fmaxf(m, pmax[(int64_t)sl * nt + i]);
+    }
+    L.ylt[i] = (float)fmin(fmax(S - (double)L.aggR, 0.0), (double)L.aggL);    // aggregate terms
+    if (L.omax) L.omax[i] = m;
+}
+
+// Large catalogs: one wavefront per trial gathers the table through L2.
+__global__ __launch_bounds__(256) void k_mean_gather(YetDev y, int64_t t0, int64_t t1,
+                                                     const LayerDev* __restrict__ layers, int32_t n_layers)
+{
+    const int lane = lane_id();
+    const int64_t trial = t0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (trial >= t1) return;
     int64_t row;
     int32_t len;
     trial_range(y, trial, row, len);
-    const bool vec = ((row & 3) == 0) && ((len & 3) == 0);
     for (int32_t l = 0; l < n_layers; ++l) {
         const LayerDev& L = layers[l];
-        const float* __restrict__ tab = L.occ_tab;
         float S = 0.0f, Sc = 0.0f, omax = 0.0f;
-        if (vec) {
-            typedef int v4i __attribute__((ext_vector_type(4)));
-            const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(y.ev + row);
-            const int32_t n4 = len >> 2;
-#pragma unroll 4
-            for (int32_t q = lane; q < n4; q += 64) {
-                const v4i e = __builtin_nontemporal_load(v4 + q);
-                const float a = tab[e.x], b = tab[e.y], c = tab[e.z], d = tab[e.w];
-                neumaier_add(S, Sc, a);
-                neumaier_add(S, Sc, b);
-                neumaier_add(S, Sc, c);
-                neumaier_add(S, Sc, d);
-                omax = fmaxf(omax, fmaxf(fmaxf(a, b), fmaxf(c, d)));
-            }
-        } else {
-            for (int32_t k = lane; k < len; k += 64) {
-                const float a = tab[y.ev[row + k]];
-                neumaier_add(S, Sc, a);
-                omax = fmaxf(omax, a);
-            }
+        for (int32_t k = lane; k < len; k += 64) {
+            const float a = L.occ_tab[y.ev[row + k]];
+            neumaier_add(S, Sc, a);
+            omax = fmaxf(omax, a);
         }
         wave_sum_pair(S, Sc);
         omax = wave_max(omax);
@@ -704,18 +865,64 @@ static void launch_layers_wpb(int mode, bool has_corr, const YetDev& y, int64_t 
 {
     const int64_t n = t1 - t0;
     const dim3 grid(nblocks(n, WPB)), block(64 * WPB);
-    if (mode == 0)
-        hipLaunchKernelGGL(k_layer_mean<WPB>, grid, block, 0, s, y, t0, t1, layers, n_layers);
-    else if (has_corr)
+    if (has_corr)
         hipLaunchKernelGGL((k_layer_plain<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
     else
         hipLaunchKernelGGL((k_layer_plain<false, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+}
+
+int32_t mean_slices(int32_t C)
+{
+    const int32_t ns = (C + kSliceMax - 1) / kSliceMax;
+    return ns <= kMaxSlices ? ns : 0;
+}
+
+int32_t mean_slice_len(int32_t C)
+{
+    const int32_t ns = mean_slices(C);
+    return ns ? (((C + ns - 1) / ns + 3) & ~3) : 0;       // a multiple of 4, at most kSliceMax
+}
+
+size_t mean_workspace_bytes(int32_t C, int64_t n_trials)
+{
+    return (size_t)std::max<int32_t>(1, mean_slices(C)) * (size_t)n_trials * 12;
+}
+
+hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStream_t s)
+{
+    const int32_t ns = mean_slices(y.C);
+    if (y.N <= 0 || ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_yet_slice, dim3(nblocks(y.N, 4)), dim3(256), 0, s, y, mean_slice_len(y.C), ns, ev2, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
+                       const int32_t* ev2, const int32_t* seg, void* ws, hipStream_t s)
+{
+    const int64_t nt = t1 - t0;
+    if (nt <= 0 || n_layers <= 0) return hipSuccess;
+    const int32_t ns = mean_slices(y.C);
+    if (ns == 0) {
+        hipLaunchKernelGGL(k_mean_gather, dim3(nblocks(nt, 4)), dim3(256), 0, s, y, t0, t1, layers, n_layers);
+        return hipGetLastError();
+    }
+    const int64_t n_tiles = (nt + kMeanTile - 1) / kMeanTile;
+    float2* part = (float2*)ws;
+    float* pmax = (float*)((char*)ws + (size_t)ns * nt * 8);
+    for (int32_t l = 0; l < n_layers; ++l) {
+        hipLaunchKernelGGL(k_mean_slice, dim3((unsigned)(n_tiles * ns)), dim3(64 * kMeanWaves), 0, s, y, t0, t1,
+                           layers, l, ev2, seg, mean_slice_len(y.C), ns, part, pmax);
+        hipLaunchKernelGGL(k_mean_finish, dim3(nblocks(nt, 256)), dim3(256), 0, s, layers, l, nt, ns,
+                           (const float2*)part, (const float*)pmax);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers,
                          int32_t n_layers, int32_t wpb, hipStream_t s)
 {
     if (t1 - t0 <= 0 || n_layers <= 0) return hipSuccess;
+    (void)mode;
     switch (wpb) {
         case 1: launch_layers_wpb<1>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
         case 2: launch_layers_wpb<2>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
