@@ -85,7 +85,7 @@ def lib():
         L.orc_run_layer.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                     C.POINTER(_Elt), C.c_int32, C.POINTER(_Terms), C.c_uint32,
                                     C.c_uint32, C.c_int32, C.c_double, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_int32]
+                                    C.c_void_p, C.c_void_p, C.c_int32]
         L.orc_max_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -162,10 +162,12 @@ def max_threads() -> int:
 # ---------------------------------------------------------------- Algorithm 1
 def run_layer(layer, yet_rows: np.ndarray, trial_ids: Sequence[int], catalog_size: int,
               seed: int, mode: int = MODE_PLAIN, threads: int = 0,
-              clamp_c: float = SIGMA_CLAMP, program_id: Optional[int] = None):
+              clamp_c: float = SIGMA_CLAMP, program_id: Optional[int] = None, yelt: bool = False):
     """Year losses of ``layer`` for the given trials (FP64).
 
-    Returns (ylt, gross, max_occ), each float64 [n_rows].
+    Returns (ylt, gross, max_occ), each float64 [n_rows], and with yelt=True
+    also the per-occurrence losses net of XELT and occurrence terms,
+    float64 [n_rows][K].
     """
     yet_rows = np.ascontiguousarray(yet_rows, dtype=np.int32)
     tid = np.ascontiguousarray(trial_ids, dtype=np.int64)
@@ -187,14 +189,16 @@ def run_layer(layer, yet_rows: np.ndarray, trial_ids: Sequence[int], catalog_siz
     ylt = np.empty(n_rows)
     gross = np.empty(n_rows)
     omax = np.empty(n_rows)
+    ye = np.zeros((n_rows, K)) if yelt else None
     prog = layer.program_id if program_id is None else program_id
     rc = lib().orc_run_layer(yet_rows.ctypes.data, tid.ctypes.data, n_rows, K, catalog_size,
                              elts, len(layer.elts), C.byref(terms), int(seed) & 0xFFFFFFFF,
                              int(prog) & 0xFFFFFFFF, int(mode), float(clamp_c),
-                             ylt.ctypes.data, gross.ctypes.data, omax.ctypes.data, int(threads))
+                             ylt.ctypes.data, gross.ctypes.data, omax.ctypes.data,
+                             None if ye is None else ye.ctypes.data, int(threads))
     if rc != 0:
         raise ValueError("event id outside the catalog")
-    return ylt, gross, omax
+    return (ylt, gross, omax, ye) if yelt else (ylt, gross, omax)
 
 
 # ---------------------------------------------------------------- section 2.4

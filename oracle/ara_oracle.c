@@ -339,13 +339,16 @@ static double clamp_xl(double l, double retention, double limit)
  * trial numbers (the RNG counter).  Outputs per selected trial: ylt (the
  * trial's year loss), gross (sum of share * loss over all draws, the scale of
  * the GPU tolerance) and max_occ (the largest occurrence loss net of
- * occurrence terms).  Returns 0, or -1 for an event ID outside the catalog.
+ * occurrence terms).  yelt (optional, n_rows x K) receives each event
+ * occurrence's loss net of XELT and occurrence terms, the quantity the
+ * aggregate terms are applied to the sum of (section 2.4's per-occurrence
+ * view).  Returns 0, or -1 for an event ID outside the catalog.
  */
 int orc_run_layer(const int32_t *yet_rows, const int64_t *trial_ids, int64_t n_rows,
                   int32_t K, int32_t C, const orc_elt *elts, int32_t n_elts,
                   const orc_layer_terms *lt, uint32_t seed, uint32_t program_id,
                   int32_t mode, double clamp_c, double *ylt, double *gross,
-                  double *max_occ, int32_t n_threads)
+                  double *max_occ, double *yelt, int32_t n_threads)
 {
     /* Stage 1 (section 2.2, preprocessing): direct-access tables, one per
      * XELT, indexed by event ID over the catalog (section 4.1). */
@@ -406,6 +409,7 @@ int orc_run_layer(const int32_t *yet_rows, const int64_t *trial_ids, int64_t n_r
                 lT += X->share * clamp_xl(loss, X->deductible, X->limit);   /* terms I */
             }
             double o = clamp_xl(lT, lt->occ_retention, lt->occ_limit);     /* occurrence terms */
+            if (yelt) yelt[r * (int64_t)K + k] = o;
             if (o > omax) omax = o;
             double t = S + o;                             /* Neumaier-compensated sum */
             if (fabs(S) >= fabs(o)) Scomp += (S - t) + o; else Scomp += (o - t) + S;

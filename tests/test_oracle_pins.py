@@ -232,9 +232,10 @@ def test_terms_hand_worked(orc, mode):
     for case in w["cases"]:
         _, lay = _w1_layer(case["override"])
         rows = np.array([case["trial"]], dtype=np.int32)
-        y, g, om = orc.run_layer(lay, rows, [0], w["catalog_size"], seed=1, mode=mode)
+        y, g, om, ye = orc.run_layer(lay, rows, [0], w["catalog_size"], seed=1, mode=mode, yelt=True)
         assert y[0] == case["Y"]
         assert om[0] == case["max_occ"]
+        assert list(ye[0]) == case["yelt"]                      # per-occurrence losses (YELT)
 
 
 def test_risk_measures_hand_worked(orc):
