@@ -260,6 +260,11 @@ def main():
                                                args.steps, args.warmup)
     value = N * K / step_s
     log(f"plain: {step_s * 1e3:.2f} ms/step, layer kernel {kernel_ms:.2f} ms")
+    # occurrence exceedance beside the aggregate: PML/TVaR of the largest occurrence loss per trial (untimed)
+    om = torch.empty(N, dtype=torch.float32, device="cuda")
+    P.ara_run_layer_ex(eng.ctx, yh, desc, P.MODE_PLAIN, wl.seed, 0, N, out, om)
+    oep_pml, oep_tvar = P.ara_risk_measures(eng.ctx, om, rps)
+    del om
     ach = VALU_OPS_PER_DRAW * draws / (kernel_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
             "traffic": TRAFFIC_BYTES if N == 800_000 else None, "kernel": "k_layer_plain", "kernel_ms": kernel_ms,
@@ -313,6 +318,8 @@ def main():
         "serving": serve,
         "cpu_baseline": cpu,
         "pml": [float(v) for v in pml], "tvar": [float(v) for v in tvar],
+        "oep": {"pml": [float(v) for v in oep_pml], "tvar": [float(v) for v in oep_tvar],
+                "note": "PML/TVaR of the largest occurrence loss per trial (occurrence exceedance)"},
         "context": {"paper_c2075_trial_events_per_s": 8e8 / 41.0,
                     "note": "paper: 800k x 1,000 in 41 s on a Tesla C2075 with ~0.3 draws per trial-event; "
                             "this workload has ~5.3 draws per trial-event"},

@@ -138,6 +138,22 @@ ara_status ara_run_layer_ex(ara_ctx *ctx, int32_t yet_handle, const ara_layer_de
                             float *ylt_out, float *max_occ_out, void *hip_stream);
 
 /*
+ * Year event loss table: the per-occurrence view behind the year losses
+ * (section 2.4; the occurrence exceedance basis).  As ara_run_layer_ex, and
+ * yelt_out receives, for every event occurrence k of every trial i in
+ * [trial_begin, trial_end), its loss net of XELT and occurrence terms --
+ * the values whose sum the aggregate terms turn into the year loss -- at
+ * yelt_out[row(i) + k - row(trial_begin)], where row(i) = i * K for a
+ * fixed-length YET and trial_offsets[i] otherwise.  yelt_out: float, device
+ * (asynchronous) or host (synchronous), row(trial_end) - row(trial_begin)
+ * entries; must not be NULL.  ylt_out and max_occ_out are exactly what
+ * ara_run_layer_ex writes for the same arguments.
+ */
+ara_status ara_run_layer_yelt(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layer,
+                              ara_mode mode, uint32_t seed, int64_t trial_begin, int64_t trial_end,
+                              float *ylt_out, float *max_occ_out, float *yelt_out, void *hip_stream);
+
+/*
  * A batch of layers over one YET in one launch: each trial tile's event ids
  * are read from HBM once and evaluated for every layer.  ylt_outs[l] receives
  * layer l's YLT (device pointers only).

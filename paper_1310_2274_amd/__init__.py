@@ -69,6 +69,7 @@ def lib() -> C.CDLL:
             "ara_free_elts": (i32, [vp, C.POINTER(i32), i32]),
             "ara_run_layer": (i32, [vp, i32, C.POINTER(LayerDesc), C.c_int, u32, vp, vp]),
             "ara_run_layer_ex": (i32, [vp, i32, C.POINTER(LayerDesc), C.c_int, u32, i64, i64, vp, vp, vp]),
+            "ara_run_layer_yelt": (i32, [vp, i32, C.POINTER(LayerDesc), C.c_int, u32, i64, i64, vp, vp, vp, vp]),
             "ara_run_layers": (i32, [vp, i32, C.POINTER(LayerDesc), i32, C.c_int, u32, C.POINTER(vp), vp]),
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
@@ -224,6 +225,14 @@ def ara_run_layer_ex(ctx, yet_handle: int, layer: LayerDesc, mode: int, seed: in
     _check(ctx, lib().ara_run_layer_ex(ctx, int(yet_handle), C.byref(layer), int(mode), int(seed) & 0xFFFFFFFF,
                                        int(trial_begin), int(trial_end), _ptr(ylt_out), _ptr(max_occ_out),
                                        _stream(stream, ylt_out, max_occ_out)))
+
+
+def ara_run_layer_yelt(ctx, yet_handle: int, layer: LayerDesc, mode: int, seed: int, trial_begin: int,
+                       trial_end: int, ylt_out, yelt_out, max_occ_out=None, stream=None) -> None:
+    """Year losses plus the per-occurrence losses (YELT) in the YET's layout."""
+    _check(ctx, lib().ara_run_layer_yelt(ctx, int(yet_handle), C.byref(layer), int(mode), int(seed) & 0xFFFFFFFF,
+                                         int(trial_begin), int(trial_end), _ptr(ylt_out), _ptr(max_occ_out),
+                                         _ptr(yelt_out), _stream(stream, ylt_out, max_occ_out, yelt_out)))
 
 
 def ara_run_layers(ctx, yet_handle: int, layers: Sequence[LayerDesc], mode: int, seed: int, ylt_outs,

@@ -31,6 +31,7 @@ struct YetRec {
     DevBuf ev, offs;
     DevBuf sev, sseg;     // mean mode: slice-major copy of the ids and its group offsets (built on first use)
     bool sliced = false;
+    std::vector<int64_t> hoffs;   // host copy of the trial offsets (variable-length YETs)
     int64_t N = 0, total = 0;
     int32_t K = 0, C = 0;
 };
@@ -348,7 +349,7 @@ ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
 }
 
 ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const YetDev& yd, int64_t t0, int64_t t1,
-                       const LayerDev* layers_dev, int32_t n_layers, int32_t maxJ, hipStream_t s)
+                       const LayerDev* layers_dev, int32_t n_layers, int32_t maxJ, hipStream_t s, bool yelt = false)
 {
     if (mode == ARA_MODE_MEAN) {
         ara_status st = ws_reserve(c, c->ws_mean, mean_workspace_bytes(yd.C, t1 - t0));
@@ -363,7 +364,7 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
                                           s));
     else if (mode == ARA_MODE_MEAN)
         HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const int32_t*)yr.sseg.p,
-                              c->ws_mean.p, s));
+                              c->ws_mean.p, yelt, s));
     else
         HIPCHK(c, launch_layers(1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
     if (c->profiling) {
@@ -375,7 +376,7 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
 
 ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
                     uint32_t seed, int64_t t0, int64_t t1, float* const* ylt_outs, float* const* omax_outs,
-                    void* hip_stream, bool allow_host_out)
+                    float* const* yelt_outs, void* hip_stream, bool allow_host_out)
 {
     if (!c) return ARA_E_STATE;
     if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
@@ -405,16 +406,26 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
         maxJ = std::max(maxJ, plans[l].dev.J);
     }
     const int64_t n = t1 - t0;
+    // occurrences of trials [t0, t1): rows r0 .. r1 of the YET
+    const int64_t r0 = y.hoffs.empty() ? t0 * (int64_t)y.K : y.hoffs[(size_t)t0];
+    const int64_t r1 = y.hoffs.empty() ? t1 * (int64_t)y.K : y.hoffs[(size_t)t1];
     // host outputs go through a device staging buffer
-    std::vector<bool> host_out((size_t)n_layers, false), host_om((size_t)n_layers, false);
+    std::vector<bool> host_out((size_t)n_layers, false), host_om((size_t)n_layers, false),
+        host_ye((size_t)n_layers, false);
     size_t out_bytes = 0;
+    bool any_yelt = false;
     for (int32_t l = 0; l < n_layers; ++l) {
         if (!ylt_outs[l]) return fail(c, ARA_E_INVAL, "ylt output %d is NULL", l);
         host_out[l] = !is_device_ptr(ylt_outs[l]);
         if (omax_outs && omax_outs[l]) host_om[l] = !is_device_ptr(omax_outs[l]);
-        if ((host_out[l] || host_om[l]) && !allow_host_out)
+        if (yelt_outs && yelt_outs[l]) {
+            host_ye[l] = !is_device_ptr(yelt_outs[l]);
+            any_yelt = true;
+        }
+        if ((host_out[l] || host_om[l] || host_ye[l]) && !allow_host_out)
             return fail(c, ARA_E_INVAL, "batched runs need device output buffers");
-        out_bytes += (host_out[l] ? align256((size_t)n * 4) : 0) + (host_om[l] ? align256((size_t)n * 4) : 0);
+        out_bytes += (host_out[l] ? align256((size_t)n * 4) : 0) + (host_om[l] ? align256((size_t)n * 4) : 0) +
+                     (host_ye[l] ? align256((size_t)(r1 - r0) * 4) : 0);
     }
     if ((st = ws_reserve(c, c->ws_tab, tab_total))) return st;
     if (out_bytes && (st = ws_reserve(c, c->ws_out, out_bytes))) return st;
@@ -442,6 +453,15 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
         } else {
             p.dev.ylt = ylt_outs[l];
         }
+        if (yelt_outs && yelt_outs[l]) {
+            if (host_ye[l]) {
+                p.dev.yelt = (float*)ob;
+                ob += align256((size_t)(r1 - r0) * 4);
+            } else {
+                p.dev.yelt = yelt_outs[l];
+            }
+            p.dev.yelt_base = r0;
+        }
         if (omax_outs && omax_outs[l]) {
             if (host_om[l]) {
                 p.dev.omax = (float*)ob;
@@ -457,7 +477,8 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     StageSlot* sl2 = nullptr;
     if ((st = stage(c, devs.data(), devs.size() * sizeof(LayerDev), s, &layers_dev, &sl2))) return st;
     YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
-    if ((st = launch_mode(c, mode, has_corr, y, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, maxJ, s))) return st;
+    if ((st = launch_mode(c, mode, has_corr, y, yd, t0, t1, (const LayerDev*)layers_dev, n_layers, maxJ, s, any_yelt)))
+        return st;
     if ((st = release_stage(c, sl1, s))) return st;
     if ((st = release_stage(c, sl2, s))) return st;
     bool sync = false;
@@ -468,6 +489,10 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
         }
         if (omax_outs && omax_outs[l] && host_om[l]) {
             HIPCHK(c, hipMemcpyAsync(omax_outs[l], devs[l].omax, (size_t)n * 4, hipMemcpyDeviceToHost, s));
+            sync = true;
+        }
+        if (yelt_outs && yelt_outs[l] && host_ye[l] && r1 > r0) {
+            HIPCHK(c, hipMemcpyAsync(yelt_outs[l], devs[l].yelt, (size_t)(r1 - r0) * 4, hipMemcpyDeviceToHost, s));
             sync = true;
         }
     }
@@ -642,6 +667,7 @@ ara_status ara_load_yet(ara_ctx* c, const int32_t* event_ids, const int64_t* tri
     YetRec y;
     y.N = n_trials;
     y.total = total;
+    if (trial_offsets) y.hoffs.assign(trial_offsets, trial_offsets + n_trials + 1);
     y.K = trial_offsets ? 0 : events_per_trial;
     y.C = catalog_size;
     if ((st = dev_alloc(c, y.ev, (size_t)total * 4))) return st;
@@ -685,6 +711,8 @@ ara_status ara_free_yet(ara_ctx* c, int32_t h)
     dev_free(c, c->yets[h].offs);
     dev_free(c, c->yets[h].sev);
     dev_free(c, c->yets[h].sseg);
+    c->yets[h].hoffs.clear();
+    c->yets[h].hoffs.shrink_to_fit();
     c->yets[h].sliced = false;
     c->yets[h].live = false;
     return ARA_OK;
@@ -797,7 +825,7 @@ ara_status ara_run_layer(ara_ctx* c, int32_t yh, const ara_layer_desc* layer, ar
     if (!c) return ARA_E_STATE;
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
     float* outs[1] = {ylt_out};
-    return run_impl(c, yh, layer, 1, mode, seed, 0, c->yets[yh].N, outs, nullptr, hip_stream, true);
+    return run_impl(c, yh, layer, 1, mode, seed, 0, c->yets[yh].N, outs, nullptr, nullptr, hip_stream, true);
 }
 
 ara_status ara_run_layer_ex(ara_ctx* c, int32_t yh, const ara_layer_desc* layer, ara_mode mode, uint32_t seed,
@@ -806,7 +834,19 @@ ara_status ara_run_layer_ex(ara_ctx* c, int32_t yh, const ara_layer_desc* layer,
 {
     float* outs[1] = {ylt_out};
     float* om[1] = {max_occ_out};
-    return run_impl(c, yh, layer, 1, mode, seed, trial_begin, trial_end, outs, om, hip_stream, true);
+    return run_impl(c, yh, layer, 1, mode, seed, trial_begin, trial_end, outs, om, nullptr, hip_stream, true);
+}
+
+ara_status ara_run_layer_yelt(ara_ctx* c, int32_t yh, const ara_layer_desc* layer, ara_mode mode, uint32_t seed,
+                              int64_t trial_begin, int64_t trial_end, float* ylt_out, float* max_occ_out,
+                              float* yelt_out, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (!yelt_out) return fail(c, ARA_E_INVAL, "yelt_out is NULL");
+    float* outs[1] = {ylt_out};
+    float* om[1] = {max_occ_out};
+    float* ye[1] = {yelt_out};
+    return run_impl(c, yh, layer, 1, mode, seed, trial_begin, trial_end, outs, om, ye, hip_stream, true);
 }
 
 ara_status ara_run_layers(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
@@ -814,7 +854,7 @@ ara_status ara_run_layers(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, 
 {
     if (!c) return ARA_E_STATE;
     if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
-    return run_impl(c, yh, layers, n_layers, mode, seed, 0, c->yets[yh].N, ylt_outs, nullptr, hip_stream, false);
+    return run_impl(c, yh, layers, n_layers, mode, seed, 0, c->yets[yh].N, ylt_outs, nullptr, nullptr, hip_stream, false);
 }
 
 

@@ -33,6 +33,8 @@ struct LayerDev {
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
     float* ylt;             // [trial_end - trial_begin]
     float* omax;            // [trial_end - trial_begin] or null
+    float* yelt;            // per occurrence, in the YET's layout from row(trial_begin), or null
+    int64_t yelt_base;      // row(trial_begin)
     float occR, occL, aggR, aggL;
     uint32_t prog;
     uint32_t seed;          // key word of this layer's random numbers
@@ -71,7 +73,7 @@ int32_t mean_slices(int32_t C);
 size_t mean_workspace_bytes(int32_t C, int64_t n_trials);
 hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStream_t s);
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const int32_t* seg, void* ws, hipStream_t s);
+                       const int32_t* ev2, const int32_t* seg, void* ws, bool yelt, hipStream_t s);
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
                          const LayerDev* layers, int32_t n_layers, int32_t wpb, hipStream_t s);
 

@@ -261,6 +261,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                 const float o = xl(PC[r][lane], L.occR, L.occL);
                 omax = fmaxf(omax, o);
                 neumaier_add(S, Sc, o);
+                if (L.yelt) L.yelt[row + ci * kChunk + lane - L.yelt_base] = o;
                 PN[r][lane] = kFinal;
             }
             if (__ballot(PN[r][lane] != kFinal) == 0ull) RC[r] = -1;
@@ -601,6 +602,20 @@ __global__ __launch_bounds__(256) void k_mean_finish(const LayerDev* __restrict_
     if (L.omax) L.omax[i] = m;
 }
 
+// Per-occurrence output of the mean mode: each occurrence's tabulated loss,
+// in the YET's layout (written beside the sums, which it does not change).
+__global__ __launch_bounds__(256) void k_mean_yelt(YetDev y, int64_t t0, int64_t t1,
+                                                   const LayerDev* __restrict__ layers, int32_t l)
+{
+    const LayerDev& L = layers[l];
+    if (!L.yelt) return;
+    const int64_t r0 = y.offs ? y.offs[t0] : t0 * (int64_t)y.K;
+    const int64_t r1 = y.offs ? y.offs[t1] : t1 * (int64_t)y.K;
+    for (int64_t r = r0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < r1;
+         r += (int64_t)gridDim.x * blockDim.x)
+        L.yelt[r - L.yelt_base] = L.occ_tab[y.ev[r]];
+}
+
 // Large catalogs: one wavefront per trial gathers the table through L2.
 __global__ __launch_bounds__(256) void k_mean_gather(YetDev y, int64_t t0, int64_t t1,
                                                      const LayerDev* __restrict__ layers, int32_t n_layers)
@@ -897,10 +912,13 @@ hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStre
 }
 
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const int32_t* seg, void* ws, hipStream_t s)
+                       const int32_t* ev2, const int32_t* seg, void* ws, bool yelt, hipStream_t s)
 {
     const int64_t nt = t1 - t0;
     if (nt <= 0 || n_layers <= 0) return hipSuccess;
+    if (yelt)
+        for (int32_t l = 0; l < n_layers; ++l)
+            hipLaunchKernelGGL(k_mean_yelt, dim3(2048), dim3(256), 0, s, y, t0, t1, layers, l);
     const int32_t ns = mean_slices(y.C);
     if (ns == 0) {
         hipLaunchKernelGGL(k_mean_gather, dim3(nblocks(nt, 4)), dim3(256), 0, s, y, t0, t1, layers, n_layers);

@@ -528,6 +528,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                 const float o = xl(c, L.occR, L.occL);
                 omax = fmaxf(omax, o);
                 neumaier_add(S, Sc, o);
+                if (L.yelt) L.yelt[row + k - L.yelt_base] = o;
             }
         }
         wave_sum_pair(S, Sc);
