@@ -157,6 +157,47 @@ def portfolio_leg(P, torch, synth, steps):
     return res
 
 
+def correlated_leg(P, torch, synth, steps):
+    """10 programs x 2 layers sharing ELTs with correlated std (sigma_C > 0),
+    program and portfolio totals and their PML/TVaR; the same portfolio with
+    sigma_C = 0 beside it."""
+    res = {}
+    rps = P.DEFAULT_RETURN_PERIODS
+    for name, frac in (("correlated", 0.6), ("independent", 0.0)):
+        wl = synth.correlated_portfolio(n_programs=10, layers_per_program=2, n_trials=200_000, sigma_c_frac=frac)
+        eng = P.Engine(0)
+        yh = eng.load_yet(wl.yet(), wl.catalog_size)
+        descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
+        N = wl.n_trials
+        outs = [torch.empty(N, device="cuda") for _ in descs]
+        progs = sorted({l.program_id for l in wl.layers})
+        ptot = [torch.empty(N, device="cuda") for _ in progs]
+        total = torch.empty(N, device="cuda")
+
+        def step():
+            P.ara_run_layers(eng.ctx, yh, descs, P.MODE_PLAIN, wl.seed, outs)
+            for k, p in enumerate(progs):
+                P.ara_sum_ylts(eng.ctx, [outs[l] for l, lay in enumerate(wl.layers) if lay.program_id == p], ptot[k])
+            P.ara_sum_ylts(eng.ctx, ptot, total)
+            return P.ara_risk_measures(eng.ctx, total, rps)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pml, tvar = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res[name] = {"ms_per_step": dt * 1e3, "trial_events_per_s": len(descs) * wl.trial_events / dt,
+                     "portfolio_pml": [float(v) for v in pml], "portfolio_tvar": [float(v) for v in tvar]}
+        log(f"correlated portfolio ({name}): {dt * 1e3:.1f} ms for {len(descs)} layers + totals")
+        eng.close()
+    res["workload"] = (f"200000 trials x 1000 events, 10 programs x 2 layers over a shared pool of 24 ELTs "
+                       f"(10k-40k entries), sigma_C share U(0, 0.6) of each std; one launch for all layers, "
+                       f"program and portfolio totals, portfolio PML/TVaR")
+    return res
+
+
 def serving_leg(P, torch, synth, rate, n_warm, n_meas, mode_name):
     from paper_1310_2274_amd import serving
     wl = synth.serving_yet()
@@ -212,6 +253,8 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--sur-ckpt", default="")
     ap.add_argument("--portfolio", action="store_true", help="add the 64-layer portfolio-batch leg")
+    ap.add_argument("--correlated", action="store_true",
+                    help="add the correlated multi-program portfolio leg (sigma_C > 0, program totals)")
     ap.add_argument("--serve", default="", help="serving leg: comma-separated request rates, e.g. 5,20")
     ap.add_argument("--serve-mode", default="plain", choices=["plain", "surrogate"])
     ap.add_argument("--serve-requests", type=int, default=600)
@@ -292,6 +335,7 @@ def main():
     eng.close()
 
     port = portfolio_leg(P, torch, synth, max(1, args.steps // 2)) if args.portfolio else None
+    corr = correlated_leg(P, torch, synth, max(1, args.steps // 2)) if args.correlated else None
     serve = None
     if args.serve:
         serve = [serving_leg(P, torch, synth, float(r), args.serve_warmup, args.serve_requests, args.serve_mode)
@@ -315,6 +359,7 @@ def main():
         "trial_tile": tune or None,
         "surrogate": sur,
         "portfolio": port,
+        "correlated_portfolio": corr,
         "serving": serve,
         "cpu_baseline": cpu,
         "pml": [float(v) for v in pml], "tvar": [float(v) for v in tvar],

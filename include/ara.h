@@ -193,6 +193,18 @@ ara_status ara_autotune(ara_ctx *ctx, int32_t yet_handle, const int32_t *layer_h
                         int64_t n_trials, int32_t *best_wpb_out, float *ms_out);
 
 /*
+ * Portfolio and program totals (section 2.1: a portfolio is a set of
+ * programs, a program a set of layers): out[i] = the sum over l of
+ * ylts[l][i] for i < n_trials, accumulated in FP64 in the order given and
+ * rounded to FP32.  ylts: host array of n device pointers (n <= 32768), out:
+ * device; asynchronous on hip_stream.  PML/TVaR of a total (ara_risk_measures)
+ * are the program- or portfolio-level measures; a total without one program
+ * gives that program's marginal contribution.
+ */
+ara_status ara_sum_ylts(ara_ctx *ctx, const float *const *ylts, int32_t n, int64_t n_trials, float *out,
+                        void *hip_stream);
+
+/*
  * PML and TVaR (section 2.4) of a YLT of n_trials floats (device or host):
  * for each return period RP, k = floor(n_trials / RP) (ARA_E_RANGE if k < 1);
  * PML = the k-th largest year loss; TVaR = the mean of the k largest, summed in

@@ -72,6 +72,7 @@ def lib() -> C.CDLL:
             "ara_run_layer_yelt": (i32, [vp, i32, C.POINTER(LayerDesc), C.c_int, u32, i64, i64, vp, vp, vp, vp]),
             "ara_run_layers": (i32, [vp, i32, C.POINTER(LayerDesc), i32, C.c_int, u32, C.POINTER(vp), vp]),
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
+            "ara_sum_ylts": (i32, [vp, C.POINTER(vp), i32, i64, vp, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
             "ara_set_profiling": (i32, [vp, i32]),
             "ara_prepare_layer": (i32, [vp, C.POINTER(LayerDesc), C.c_int, C.POINTER(i32)]),
@@ -233,6 +234,14 @@ def ara_run_layer_yelt(ctx, yet_handle: int, layer: LayerDesc, mode: int, seed: 
     _check(ctx, lib().ara_run_layer_yelt(ctx, int(yet_handle), C.byref(layer), int(mode), int(seed) & 0xFFFFFFFF,
                                          int(trial_begin), int(trial_end), _ptr(ylt_out), _ptr(max_occ_out),
                                          _ptr(yelt_out), _stream(stream, ylt_out, max_occ_out, yelt_out)))
+
+
+def ara_sum_ylts(ctx, ylts, out, n_trials: Optional[int] = None, stream=None) -> None:
+    """out[i] = sum of ylts[l][i] (FP64 accumulation); device tensors or raw device addresses."""
+    n = len(ylts)
+    arr = (C.c_void_p * n)(*[v if isinstance(v, int) else v.data_ptr() for v in ylts])
+    nt = int(n_trials if n_trials is not None else out.shape[0])
+    _check(ctx, lib().ara_sum_ylts(ctx, arr, n, nt, _ptr(out), _stream(stream, out, *[v for v in ylts if not isinstance(v, int)])))
 
 
 def ara_run_layers(ctx, yet_handle: int, layers: Sequence[LayerDesc], mode: int, seed: int, ylt_outs,

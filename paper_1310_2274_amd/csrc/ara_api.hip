@@ -1006,6 +1006,26 @@ ara_status ara_autotune(ara_ctx* c, int32_t yh, const int32_t* handles, int32_t 
     return ARA_OK;
 }
 
+ara_status ara_sum_ylts(ara_ctx* c, const float* const* ylts, int32_t n, int64_t n_trials, float* out,
+                        void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 1 || !ylts || !out || n_trials < 0) return fail(c, ARA_E_INVAL, "bad arguments to ara_sum_ylts");
+    if (n > (int32_t)(kStageBytes / sizeof(float*))) return fail(c, ARA_E_INVAL, "too many YLTs (%d)", n);
+    if (!is_device_ptr(out)) return fail(c, ARA_E_INVAL, "out must be device memory");
+    for (int32_t l = 0; l < n; ++l)
+        if (!ylts[l] || !is_device_ptr(ylts[l])) return fail(c, ARA_E_INVAL, "YLT %d is not device memory", l);
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    void* dev = nullptr;
+    StageSlot* sl = nullptr;
+    if ((st = stage(c, ylts, (size_t)n * sizeof(float*), s, &dev, &sl))) return st;
+    HIPCHK(c, launch_sum_ylts((const float* const*)dev, n, n_trials, out, s));
+    if ((st = release_stage(c, sl, s))) return st;
+    return end_call(c, s);
+}
+
 ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const double* rps, int32_t n_rp, double* pml,
                              double* tvar, void* hip_stream)
 {

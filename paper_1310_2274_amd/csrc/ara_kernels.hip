@@ -950,6 +950,24 @@ hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, i
     return hipGetLastError();
 }
 
+// Portfolio and program totals: per trial, the sum of n year-loss tables in
+// FP64, in the order given.
+__global__ __launch_bounds__(256) void k_sum_ylts(const float* const* __restrict__ ylts, int32_t n, int64_t nt,
+                                                  float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    double s = 0.0;
+    for (int32_t l = 0; l < n; ++l) s += (double)ylts[l][i];
+    out[i] = (float)s;
+}
+
+hipError_t launch_sum_ylts(const float* const* ylts_dev, int32_t n, int64_t nt, float* out, hipStream_t s)
+{
+    if (nt > 0) hipLaunchKernelGGL(k_sum_ylts, dim3(nblocks(nt, 256)), dim3(256), 0, s, ylts_dev, n, nt, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_risk_measures(const float* y, int64_t n, const uint32_t* k_host, int32_t n_rp, const SelectWs& ws,
                                 hipStream_t s)
 {

@@ -164,13 +164,14 @@ def tiny(seed: int = MASTER_SEED) -> Workload:
     return Workload("tiny_1000x100_2elt", N, K, C, [lay], seed=seed, yet_seed=seed)
 
 
-def paper_scale(n_trials: int = 800_000, seed: int = MASTER_SEED) -> Workload:
+def paper_scale(n_trials: int = 800_000, seed: int = MASTER_SEED, sigma_c_frac: float = 0.0) -> Workload:
     """800,000 trials x 1,000 events over a 100,000-event catalog; one layer of
     16 ELTs with 20,000-50,000 entries each.  ``n_trials`` shrinks the YET
-    only (same tables, same first trials)."""
+    only (same tables, same first trials).  ``sigma_c_frac`` > 0 moves a
+    U(0, sigma_c_frac) share of each entry's std into the correlated part."""
     K, C = 1000, 100_000
     rng = _rng(seed, 2, 1)
-    elts = _elts(rng, C, 16, 20_000, 50_000)
+    elts = _elts(rng, C, 16, 20_000, 50_000, sigma_c_frac)
     E = K * sum(e.n for e in elts) / C
     lay = Layer(elts, occ_retention=L0, occ_limit=20 * L0,
                 agg_retention=1.12 * E * L0, agg_limit=0.17 * E * L0)
@@ -198,6 +199,33 @@ def portfolio(n_layers: int = 64, n_trials: int = 200_000, seed: int = MASTER_SE
     rng = _rng(seed, 2, 3)
     layers = [random_layer(rng, C, K, 40, 5_000, 50_000, program_id=i % 10) for i in range(n_layers)]
     return Workload(f"portfolio_{n_layers}L_{n_trials}x1000", n_trials, K, C, layers, seed=seed, yet_seed=seed)
+
+
+def correlated_portfolio(n_programs: int = 10, layers_per_program: int = 2, n_trials: int = 200_000,
+                         sigma_c_frac: float = 0.6, seed: int = MASTER_SEED) -> Workload:
+    """A portfolio of ``n_programs`` programs (section 2.1: up to 10), each of
+    ``layers_per_program`` layers, over one YET of n_trials x 1,000 events and
+    a 100,000-event catalog.  Every layer draws from the same pool of 24 ELTs
+    (1-12 of them, log-uniform), so programs cover the same events; each entry
+    carries a correlated std (a U(0, sigma_c_frac) share of its std), whose
+    uniform z_(E) is shared by every program (section 3.1)."""
+    K, C = 1000, 100_000
+    rng = _rng(seed, 2, 6)
+    pool = _elts(rng, C, 24, 10_000, 40_000, sigma_c_frac)
+    layers = []
+    for p in range(n_programs):
+        for _ in range(layers_per_program):
+            J = int(round(math.exp(rng.uniform(0.0, math.log(12)))))
+            pick = sorted(rng.choice(len(pool), size=max(1, J), replace=False).tolist())
+            elts = [pool[i] for i in pick]
+            E = K * sum(e.n for e in elts) / C
+            layers.append(Layer(elts,
+                                occ_retention=float(rng.uniform(0.5, 2.0) * L0),
+                                occ_limit=float(rng.uniform(10.0, 40.0) * L0),
+                                agg_retention=float(rng.uniform(0.5, 1.1) * E * L0),
+                                agg_limit=float(rng.uniform(0.05, 1.0) * E * L0),
+                                program_id=p))
+    return Workload(f"correlated_{n_programs}P_{n_trials}x1000", n_trials, K, C, layers, seed=seed, yet_seed=seed)
 
 
 def serving_yet(n_trials: int = 1_000_000, seed: int = MASTER_SEED) -> Workload:
