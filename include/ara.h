@@ -294,6 +294,10 @@ ara_status ara_surrogate_eval(ara_ctx *ctx, const double *a, const double *b, co
 
 ara_status ara_philox_uniforms(ara_ctx *ctx, const uint32_t *ctr, int64_t n, uint32_t key0, uint32_t key1,
                                float *out, void *hip_stream);
+/* ara_normal_quantile: Phi^-1(p[i]) for host arrays of n doubles in (0, 1)
+ * (ARA_E_INVAL otherwise), as the correlated draws of section 3.2 compute it
+ * (FP64; synchronous). */
+ara_status ara_normal_quantile(ara_ctx *ctx, const double *p, int64_t n, double *x_out);
 ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                              double *x_out, void *hip_stream);
 /* ara_beta_quantile_layer: the per-draw inverse exactly as the plain layer

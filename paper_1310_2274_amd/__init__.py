@@ -73,6 +73,7 @@ def lib() -> C.CDLL:
             "ara_run_layers": (i32, [vp, i32, C.POINTER(LayerDesc), i32, C.c_int, u32, C.POINTER(vp), vp]),
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
             "ara_sum_ylts": (i32, [vp, C.POINTER(vp), i32, i64, vp, vp]),
+            "ara_normal_quantile": (i32, [vp, vp, i64, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
             "ara_set_profiling": (i32, [vp, i32]),
             "ara_prepare_layer": (i32, [vp, C.POINTER(LayerDesc), C.c_int, C.POINTER(i32)]),
@@ -234,6 +235,14 @@ def ara_run_layer_yelt(ctx, yet_handle: int, layer: LayerDesc, mode: int, seed: 
     _check(ctx, lib().ara_run_layer_yelt(ctx, int(yet_handle), C.byref(layer), int(mode), int(seed) & 0xFFFFFFFF,
                                          int(trial_begin), int(trial_end), _ptr(ylt_out), _ptr(max_occ_out),
                                          _ptr(yelt_out), _stream(stream, ylt_out, max_occ_out, yelt_out)))
+
+
+def ara_normal_quantile(ctx, p) -> np.ndarray:
+    """Phi^-1(p) on the device, as the correlated draws compute it (FP64, host arrays)."""
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    x = np.empty_like(p)
+    _check(ctx, lib().ara_normal_quantile(ctx, p.ctypes.data, int(p.size), x.ctypes.data))
+    return x
 
 
 def ara_sum_ylts(ctx, ylts, out, n_trials: Optional[int] = None, stream=None) -> None:

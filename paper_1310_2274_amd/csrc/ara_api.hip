@@ -1122,6 +1122,24 @@ ara_status ara_philox_uniforms(ara_ctx* c, const uint32_t* ctr, int64_t n, uint3
     return ARA_OK;
 }
 
+ara_status ara_normal_quantile(ara_ctx* c, const double* p, int64_t n, double* x)
+{
+    if (!c) return ARA_E_STATE;
+    if (n < 0 || (n > 0 && (!p || !x))) return fail(c, ARA_E_INVAL, "bad arguments to ara_normal_quantile");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(p[i] > 0.0 && p[i] < 1.0)) return fail(c, ARA_E_INVAL, "p[%lld] must lie in (0,1)", (long long)i);
+    if (n == 0) return ARA_OK;
+    ara_status st = begin_call(c, nullptr);
+    if (st) return st;
+    const size_t nb = align256((size_t)n * 8);
+    if ((st = ws_reserve(c, c->ws_in, 2 * nb))) return st;
+    char* q = (char*)c->ws_in.p;
+    HIPCHK(c, hipMemcpy(q, p, (size_t)n * 8, hipMemcpyHostToDevice));
+    HIPCHK(c, launch_normal_quantile((const double*)q, n, (double*)(q + nb), nullptr));
+    HIPCHK(c, hipMemcpy(x, q + nb, (size_t)n * 8, hipMemcpyDeviceToHost));
+    return end_call(c, nullptr);
+}
+
 static ara_status beta_quantile_impl(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
                                      double* x, void* hip_stream, bool layer)
 {

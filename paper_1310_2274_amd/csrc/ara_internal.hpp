@@ -96,6 +96,7 @@ struct SelectWs {
     double* out;            // [2*kMaxRp]: pml, tvar
 };
 constexpr int kSelectBlocks = 256;
+hipError_t launch_normal_quantile(const double* p, int64_t n, double* x, hipStream_t s);
 hipError_t launch_sum_ylts(const float* const* ylts_dev, int32_t n, int64_t nt, float* out, hipStream_t s);
 hipError_t launch_risk_measures(const float* y, int64_t n, const uint32_t* k_host, int32_t n_rp,
                                 const SelectWs& ws, hipStream_t s);

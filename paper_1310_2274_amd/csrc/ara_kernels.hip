@@ -213,7 +213,7 @@ constexpr int kFinal = 1 << 30;              // pending count of a finished (or 
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 1 : 3))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : 3))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
@@ -222,6 +222,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     __shared__ uint16_t lst[WPB][kQueue];
     __shared__ uint32_t didx[WPB][kDefer];
     __shared__ uint32_t dmeta[WPB][kDefer];
+    __shared__ double dz[HAS_CORR ? WPB : 1][HAS_CORR ? kDefer : 1];
     __shared__ float pcs[WPB][kRing][64];
     __shared__ int pns[WPB][kRing][64];
     __shared__ int rchunk[WPB][kRing];
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     uint16_t* L32 = lst[w];
     uint32_t* DI = didx[w];          // deferred draws: packed entry index
     uint32_t* DM = dmeta[w];         //   slot within the trial | XELT position << 24
+    double* DZ = dz[HAS_CORR ? w : 0];  //   z (correlated layers: formed in the classify pass)
     float (*PC)[64] = pcs[w];        // pending chunks: partial event loss per slot
     int (*PN)[64] = pns[w];          //   deferred draws outstanding per slot
     int* RC = rchunk[w];             //   chunk held by each ring slot (-1: free)
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                 const uint32_t j = meta >> 24;
                 key = meta & 0xFFFFFFu;
                 const EntryRec E = L.pent[pi];
-                const double z = draw_z<HAS_CORR>(tr, key, j, L.seed, L.prog, L.pcw, pi);
+                const double z = HAS_CORR ? DZ[e] : draw_z<false>(tr, key, j, L.seed, L.prog, nullptr, pi);
                 const float loss = sample_loss(z, E);
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
@@ -363,15 +365,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                     }
                     const uint64_t b64 = __ballot(in && pol);
                     const uint64_t b32 = __ballot(in && !pol);
+                    // correlated layers: the draw's z (two uniforms, normal transforms in
+                    // FP64) is formed here, once per draw in full waves, and kept for the solve
+                    double zc = 0.0;
+                    if (HAS_CORR && in) {
+                        const uint32_t pi = QI[q], meta = QM[q];
+                        zc = draw_z<true>(tr, (uint32_t)base + (meta & 63u), meta >> 8, L.seed, L.prog, L.pcw, pi);
+                    }
                     if (in) {
                         if (pol) {
                             const int e = (dh + dn + __popcll(b64 & below)) & (kDefer - 1);
                             const uint32_t meta = QM[q];
                             DI[e] = QI[q];
                             DM[e] = ((uint32_t)base + (meta & 63u)) | ((meta >> 8) << 24);
+                            if (HAS_CORR) DZ[e] = zc;
                             QV[q] = kDeferred;
                         } else {
                             L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
+                            if (HAS_CORR) QV[q] = (float)zc;          // the FP32 solve takes z in FP32
                         }
                     }
                     n32 += __popcll(b32);
@@ -387,8 +398,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
-                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                        const float loss = E.maxl * inv_beta32((float)z, E);
+                        const float z = HAS_CORR ? QV[q] : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
+                        const float loss = E.maxl * inv_beta32(z, E);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
                     }
@@ -807,6 +818,18 @@ hipError_t launch_philox_uniforms(const uint32_t* ctr, int64_t n, uint32_t k0, u
     if (n > 0)
         hipLaunchKernelGGL(k_philox_uniforms, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                            (const uint4*)ctr, n, k0, k1, out);
+    return hipGetLastError();
+}
+
+__global__ void k_normal_quantile(const double* __restrict__ p, int64_t n, double* __restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = normal_quantile(p[i]);
+}
+
+hipError_t launch_normal_quantile(const double* p, int64_t n, double* x, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_normal_quantile, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, x);
     return hipGetLastError();
 }
 

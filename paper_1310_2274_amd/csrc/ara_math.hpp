@@ -333,6 +333,56 @@ __host__ __device__ inline float sample_loss(double z, const EntryRec& E)
     return E.maxl * (float)inv_beta(z, E);
 }
 
+// ---------------------------------------------------------------------------
+// Normal quantile Phi^-1(p) for 0 < p < 1, FP64: Wichura's algorithm AS 241
+// (PPND16, Applied Statistics 37, 1988), relative accuracy about 1e-16.  A
+// rational function of degree 7 in r = 0.180625 - q^2 around the centre
+// (|q| = |p - 1/2| <= 0.425); in the tails, of r = sqrt(-ln min(p, 1 - p))
+// shifted by 1.6 (r <= 5) or by 5.  The correlated draws of section 3.2 need
+// two per draw, so this replaces the general library routine, which is an
+// order of magnitude longer.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline double poly7(double x, double c0, double c1, double c2, double c3, double c4, double c5,
+                                        double c6, double c7)
+{
+    return ((((((c7 * x + c6) * x + c5) * x + c4) * x + c3) * x + c2) * x + c1) * x + c0;
+}
+
+__host__ __device__ inline double normal_quantile(double p)
+{
+    const double q = p - 0.5;
+    if (fabs(q) <= 0.425) {
+        const double r = 0.180625 - q * q;
+        return q *
+               poly7(r, 3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
+                     1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
+                     3.3430575583588128105e+4, 2.5090809287301226727e+3) /
+               poly7(r, 1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2, 5.3941960214247511077e+3,
+                     2.1213794301586595867e+4, 3.9307895800092710610e+4, 2.8729085735721942674e+4,
+                     5.2264952788528545610e+3);
+    }
+    double r = sqrt(-log(q < 0.0 ? p : 1.0 - p));
+    double x;
+    if (r <= 5.0) {
+        r -= 1.6;
+        x = poly7(r, 1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
+                  3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
+                  2.27238449892691845833e-2, 7.74545014278341407640e-4) /
+            poly7(r, 1.0, 2.05319162663775882187e0, 1.67638483018380384940e0, 6.89767334985100004550e-1,
+                  1.48103976427480074590e-1, 1.51986665636164571966e-2, 5.47593808499534494600e-4,
+                  1.05075007164441684324e-9);
+    } else {
+        r -= 5.0;
+        x = poly7(r, 6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
+                  2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
+                  2.71155556874348757815e-5, 2.01033439929228813265e-7) /
+            poly7(r, 1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1, 1.48753612908506148525e-2,
+                  7.86869131145613259100e-4, 1.84631831751005468180e-5, 1.42151175831644588870e-7,
+                  2.04426310338993978564e-15);
+    }
+    return q < 0.0 ? -x : x;
+}
+
 // Financial terms: min(max(l - retention, 0), limit).
 __host__ __device__ inline float xl(float l, float retention, float limit)
 {

@@ -87,7 +87,7 @@ __device__ __forceinline__ double draw_z(uint32_t trial, uint32_t slot, uint32_t
     if (w.y == 0.0f) return ui;
     const double uc = (double)u01(philox_word0(trial, slot, 0xFFFFFFFFu, 1u, seed, 0xFFFFFFFFu));
     if (w.x == 0.0f) return uc;
-    return normcdf((double)w.x * normcdfinv(ui) + (double)w.y * normcdfinv(uc));
+    return normcdf((double)w.x * normal_quantile(ui) + (double)w.y * normal_quantile(uc));
 }
 
 }  // namespace ara

@@ -102,6 +102,30 @@ def test_layer_inverse_per_draw_accuracy(eng, lo, hi, seed):
     assert np.all(x[~visible] <= 1e-28)
 
 
+def test_normal_quantile_vs_oracle_and_tables(eng):
+    # the FP64 Phi^-1 of the correlated draws (section 3.2): tabulated points,
+    # both region boundaries of the rational approximations, the ends of the
+    # 2^-24 grid, and random grid points
+    from scipy.special import ndtri
+    from conftest import golden
+    pts = golden("normal_points.json")["points"]
+    p = np.array([q["p"] for q in pts])
+    x = P.ara_normal_quantile(eng.ctx, p)
+    for q, v in zip(pts, x):
+        assert v == pytest.approx(q["x"], rel=1e-14, abs=1e-15)
+    rng = np.random.default_rng(8)
+    grid = (2 * rng.integers(0, 2 ** 23, 5000) + 1) * 2.0 ** -24
+    edges = np.array([2.0 ** -24, 1 - 2.0 ** -24, 0.075, 0.925, 0.0749999, 0.9250001, math.exp(-25.0),
+                      math.exp(-25.0) * 1.0001, 1e-300, 0.5])
+    p = np.concatenate([grid, edges])
+    x = P.ara_normal_quantile(eng.ctx, p)
+    xo = np.array([oracle.norm_quantile(v) for v in p])
+    assert np.allclose(x, xo, rtol=1e-14, atol=1e-15)
+    assert np.allclose(x, ndtri(p), rtol=1e-13, atol=1e-14)
+    with pytest.raises(P.AraError):
+        P.ara_normal_quantile(eng.ctx, np.array([0.0]))
+
+
 def test_beta_quantile_rejects_bad_input(eng):
     with pytest.raises(P.AraError) as e:
         P.ara_beta_quantile(eng.ctx, np.array([1.0]), np.array([-1.0]), np.array([0.5]))
