@@ -305,7 +305,9 @@ __device__ inline float inv_beta32(float z, const EntryRec& E)
         const float w = 1.0f - t;
         const float l1t = f32_log1m(t, w);
         float num, den;
-        beta_cf<float>(t, A, B, 2e-7f, 48, num, den);
+        // the first step only has to land near the root: a fraction good to 1e-2
+        // suffices there, and that step never ends the loop
+        beta_cf<float>(t, A, B, it == 0 ? 1e-2f : 2e-7f, 48, num, den);
         const float rnum = f32_rcp(num);
         const float f = A * y + B * l1t + c0 + f32_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
         const float dy = -(f * w * den) * (rA * rnum);
@@ -314,7 +316,7 @@ __device__ inline float inv_beta32(float z, const EntryRec& E)
         y = yn;
         // a step dy moves x by dy (lower side, x = t) or by dy * t / (1 - t)
         // relative to x (upper side, x = 1 - t)
-        if (fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
+        if (it > 0 && fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
     }
     return lower ? __expf(y) : -expm1f(y);
 }

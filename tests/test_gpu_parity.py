@@ -200,6 +200,22 @@ def test_variable_length_trials_and_empty_trials(eng):
         assert_ylt_close(y[i:i + 1], yo, g, f"trial {i}")
 
 
+def test_huge_elts_and_catalog(eng):
+    # ELTs of up to 2M entries over a 3M-event catalog (the direct-access
+    # tables of section 4.1 scale with the catalog; the mean mode's catalog
+    # no longer fits its LDS slices and reads the table through L2)
+    wl = synth.custom(600, 1000, 3_000_000, 2, 1_500_000, 2_000_000, seed=44)
+    assert max(e.n for e in wl.layers[0].elts) >= 1_500_000
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    rng = np.random.default_rng(45)
+    trials = np.unique(np.concatenate([[0, 599], rng.integers(0, 600, 30)]))
+    for mode in (oracle.MODE_MEAN, oracle.MODE_PLAIN):
+        y, om, _ = gpu_ylt(eng, wl, mode, 13, yet_handle=yh, with_omax=True)
+        yo, g, omo = oracle_ylt(wl, trials, mode, 13)
+        assert_ylt_close(y[trials], yo, g, f"huge ELTs mode={mode}")
+        assert_ylt_close(om[trials], omo, g, "max occurrence")
+
+
 # ------------------------------------------------------------ paper scale (sampled)
 def test_paper_scale_sampled_trials(eng):
     torch = torch_cuda()
