@@ -213,11 +213,11 @@ constexpr int kFinal = 1 << 30;              // pending count of a finished (or 
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : 3))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : 4))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
-    __shared__ uint32_t qmeta[WPB][kQueue];
+    __shared__ uint16_t qmeta[WPB][kQueue];
     __shared__ float qv[WPB][kQueue];
     __shared__ uint16_t lst[WPB][kQueue];
     __shared__ uint32_t didx[WPB][kDefer];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
     if (trial >= t1) return;
     uint32_t* QI = qidx[w];          // packed entry index
-    uint32_t* QM = qmeta[w];         // slot within chunk | XELT position << 8
+    uint16_t* QM = qmeta[w];         // slot within chunk | XELT position << 8
     float* QV = qv[w];               // the draw's net loss, or kDeferred
     uint16_t* L32 = lst[w];
     uint32_t* DI = didx[w];          // deferred draws: packed entry index
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                     const int j = __ffsll((unsigned long long)mask) - 1;
                     mask &= mask - 1;
                     QI[pos + i] = off + (uint32_t)(rank + i);
-                    QM[pos + i] = (uint32_t)lane | ((uint32_t)j << 8);
+                    QM[pos + i] = (uint16_t)(lane | (j << 8));
                 }
                 wave_sync();
                 // (A) classify: FP32 draws to the list, the others to the deferred ring
