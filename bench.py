@@ -37,11 +37,11 @@ PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 PEAK_VALU_TOPS = 157.3 / 2
 # VALU lane-instructions per draw of the plain layer kernel on this workload,
 # SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 1529.6
+VALU_OPS_PER_DRAW = 1400.5
 # Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2.0 * 19585239.8 + 3037.7) * 1024
+TRAFFIC_BYTES = 8 * (2.0 * 26744469.0 + 1.0 * 3032423.8) * 1024
 
 
 def log(msg):
