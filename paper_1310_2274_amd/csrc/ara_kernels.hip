@@ -192,10 +192,17 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t
 // ===========================================================================
 // The layer kernels
 // ===========================================================================
-constexpr int kWavesPerBlock = 4;
 constexpr int kChunk = 64;                   // event slots per compaction round
-constexpr int kRound = 8;                    // draws per slot per drain round
+constexpr int kRound = 6;                    // draws per slot per drain round (LDS for 20 wavefronts per CU)
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
+
+// The FP64 polish of a deferred draw, out of line: a call whose registers
+// stay out of the layer kernel's allocation (inlined, they force spills in
+// the kernel's hot loops at five wavefronts per SIMD).
+__device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E)
+{
+    return sample_loss(z, E);
+}
 
 // Plain path, one wave per trial.  Each chunk of 64 event slots is drained in
 // rounds: the queued draws of a round are classified by cost.  Draws whose
@@ -209,11 +216,11 @@ constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 // fixed function of the trial, so the result does not depend on the launch.
 constexpr int kDefer = 128;                  // deferred-draw ring per wave (power of two)
 constexpr int kRing = 4;                     // chunks that may wait for deferred draws (four register sums)
-constexpr int kFinal = 1 << 30;              // pending count of a finished (or empty) slot
+constexpr int kFinal = 0x7FFF;               // pending count of a finished (or empty) slot
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : 4))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : (WPB == 8 ? 3 : 5)))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     __shared__ uint32_t dmeta[WPB][kDefer];
     __shared__ double dz[HAS_CORR ? WPB : 1][HAS_CORR ? kDefer : 1];
     __shared__ float pcs[WPB][kRing][64];
-    __shared__ int pns[WPB][kRing][64];
+    __shared__ short pns[WPB][kRing][64];
     __shared__ int rchunk[WPB][kRing];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
     uint32_t* DM = dmeta[w];         //   slot within the trial | XELT position << 24
     double* DZ = dz[HAS_CORR ? w : 0];  //   z (correlated layers: formed in the classify pass)
     float (*PC)[64] = pcs[w];        // pending chunks: partial event loss per slot
-    int (*PN)[64] = pns[w];          //   deferred draws outstanding per slot
+    short (*PN)[64] = pns[w];        //   deferred draws outstanding per slot
     int* RC = rchunk[w];             //   chunk held by each ring slot (-1: free)
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                 key = meta & 0xFFFFFFu;
                 const EntryRec E = L.pent[pi];
                 const double z = HAS_CORR ? DZ[e] : draw_z<false>(tr, key, j, L.seed, L.prog, nullptr, pi);
-                const float loss = sample_loss(z, E);
+                const float loss = polish_loss(z, E);
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
             }
