@@ -136,7 +136,7 @@ def portfolio_leg(P, torch, synth, steps):
     yh = eng.load_yet(wl.yet(), wl.catalog_size)
     descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
     outs = [torch.empty(wl.n_trials, device="cuda") for _ in descs]
-    res = {}
+    res = {"waves_per_workgroup": autotune(P, eng, yh, descs[0], P.MODE_PLAIN, 50_000)["waves_per_workgroup"]}
     for name, mode in (("plain", P.MODE_PLAIN), ("surrogate", P.MODE_SURROGATE)):
         if mode == P.MODE_SURROGATE:
             P.ara_surrogate_train(eng.ctx, 4_000_000, epochs=10, batch=4096, lr=3e-3, seed=11)
@@ -169,6 +169,7 @@ def correlated_leg(P, torch, synth, steps):
         yh = eng.load_yet(wl.yet(), wl.catalog_size)
         descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
         N = wl.n_trials
+        tile = autotune(P, eng, yh, descs[0], P.MODE_PLAIN, min(N, 50_000))["waves_per_workgroup"]
         outs = [torch.empty(N, device="cuda") for _ in descs]
         progs = sorted({l.program_id for l in wl.layers})
         ptot = [torch.empty(N, device="cuda") for _ in progs]
@@ -189,7 +190,8 @@ def correlated_leg(P, torch, synth, steps):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         res[name] = {"ms_per_step": dt * 1e3, "trial_events_per_s": len(descs) * wl.trial_events / dt,
-                     "portfolio_pml": [float(v) for v in pml], "portfolio_tvar": [float(v) for v in tvar]}
+                     "portfolio_pml": [float(v) for v in pml], "portfolio_tvar": [float(v) for v in tvar],
+                     "waves_per_workgroup": tile}
         log(f"correlated portfolio ({name}): {dt * 1e3:.1f} ms for {len(descs)} layers + totals")
         eng.close()
     res["workload"] = (f"200000 trials x 1000 events, 10 programs x 2 layers over a shared pool of 24 ELTs "

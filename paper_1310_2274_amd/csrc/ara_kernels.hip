@@ -204,6 +204,14 @@ __device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E)
     return sample_loss(z, E);
 }
 
+// The correlated draw's z (two uniforms, two FP64 normal quantiles, one
+// normal CDF), out of line for the same reason.
+__device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed,
+                                                   uint32_t prog, const float2* pcw, uint32_t pi)
+{
+    return draw_z<true>(trial, slot, j, seed, prog, pcw, pi);
+}
+
 // Plain path, one wave per trial.  Each chunk of 64 event slots is drained in
 // rounds: the queued draws of a round are classified by cost.  Draws whose
 // smaller shape parameter is at least kPolishShape take the FP32 solve alone
@@ -220,7 +228,7 @@ constexpr int kFinal = 0x7FFF;               // pending count of a finished (or 
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CORR ? 2 : (WPB == 8 ? 3 : 5)))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(HAS_CO
                     double zc = 0.0;
                     if (HAS_CORR && in) {
                         const uint32_t pi = QI[q], meta = QM[q];
-                        zc = draw_z<true>(tr, (uint32_t)base + (meta & 63u), meta >> 8, L.seed, L.prog, L.pcw, pi);
+                        zc = corr_z(tr, (uint32_t)base + (meta & 63u), meta >> 8, L.seed, L.prog, L.pcw, pi);
                     }
                     if (in) {
                         if (pol) {
