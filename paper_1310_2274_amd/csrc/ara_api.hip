@@ -29,7 +29,7 @@ struct DevBuf {
 struct YetRec {
     bool live = false;
     DevBuf ev, offs;
-    DevBuf sev, sseg;     // mean mode: slice-major copy of the ids and its group offsets (built on first use)
+    DevBuf sev, soff, scnt;   // mean mode: slice-major copy of the ids, its group offsets and sizes (built on first use)
     bool sliced = false;
     std::vector<int64_t> hoffs;   // host copy of the trial offsets (variable-length YETs)
     int64_t N = 0, total = 0;
@@ -331,20 +331,35 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     return ARA_OK;
 }
 
-// Mean mode reads a slice-major copy of the YET, built once per YET.
+// Mean mode reads a slice-major copy of the YET, built once per YET (left
+// unbuilt, and the table read through L2, when its offsets would not fit 32
+// bits).
 ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
 {
     const int32_t ns = mean_slices(y.C);
     if (ns == 0 || y.sliced) return ARA_OK;
+    y.sliced = true;
+    const uint64_t ints = (uint64_t)y.total + (uint64_t)3 * ns * (uint64_t)y.N;
+    if (ints >= ((uint64_t)1 << 32) || y.N == 0) return ARA_OK;
+    const size_t groups = (size_t)ns * (size_t)y.N;
     ara_status st;
-    const size_t ints = (size_t)y.total + (size_t)4 * (ns + 1) * (size_t)y.N + 4;
-    if ((st = dev_alloc(c, y.sev, ints * 4))) return st;
-    if ((st = dev_alloc(c, y.sseg, (size_t)y.N * (ns + 1) * 4 + 4))) {
-        dev_free(c, y.sev);
+    DevBuf scratch;
+    if ((st = dev_alloc(c, y.scnt, groups * 4)) || (st = dev_alloc(c, y.soff, groups * 4)) ||
+        (st = dev_alloc(c, scratch, scan_scratch_words((int64_t)groups) * 4)) ||
+        (st = dev_alloc(c, y.sev, (size_t)ints * 4 + 16))) {
+        dev_free(c, y.scnt);
+        dev_free(c, y.soff);
+        dev_free(c, scratch);
+        y.sliced = false;
         return st;
     }
-    HIPCHK(c, launch_yet_slice(yd, (int32_t*)y.sev.p, (int32_t*)y.sseg.p, s));
-    y.sliced = true;
+    HIPCHK(c, launch_yet_slice_count(yd, (uint32_t*)y.scnt.p, s));
+    HIPCHK(c, launch_exclusive_scan((const uint32_t*)y.scnt.p, (uint32_t*)y.soff.p, (int64_t)groups,
+                                    (uint32_t*)scratch.p, s));
+    HIPCHK(c, launch_yet_slice_scatter(yd, (const uint32_t*)y.soff.p, (const uint32_t*)y.scnt.p, (int32_t*)y.sev.p,
+                                       s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    dev_free(c, scratch);
     return ARA_OK;
 }
 
@@ -363,8 +378,8 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
                                           (const uint32_t*)c->sur_mask.p, (const float*)c->sur_bias.p, c->wpb[mode],
                                           s));
     else if (mode == ARA_MODE_MEAN)
-        HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const int32_t*)yr.sseg.p,
-                              c->ws_mean.p, yelt, s));
+        HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const uint32_t*)yr.soff.p,
+                              (const uint32_t*)yr.scnt.p, c->ws_mean.p, yelt, s));
     else
         HIPCHK(c, launch_layers(1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
     if (c->profiling) {
@@ -710,7 +725,8 @@ ara_status ara_free_yet(ara_ctx* c, int32_t h)
     dev_free(c, c->yets[h].ev);
     dev_free(c, c->yets[h].offs);
     dev_free(c, c->yets[h].sev);
-    dev_free(c, c->yets[h].sseg);
+    dev_free(c, c->yets[h].soff);
+    dev_free(c, c->yets[h].scnt);
     c->yets[h].hoffs.clear();
     c->yets[h].hoffs.shrink_to_fit();
     c->yets[h].sliced = false;

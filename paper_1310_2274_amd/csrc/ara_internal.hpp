@@ -66,14 +66,18 @@ hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double oc
 // wpb: wavefronts (= trials) per workgroup, 1, 2, 4 or 8 -- the trial tile
 // Mean mode: catalog slices of the per-event table in LDS over a slice-major
 // copy of the YET (mean_slices() == 0: too many slices, the table is read
-// through L2 instead).  The copy of a YET with N trials and T ids holds
-// T + 4 * (ns + 1) * N + 4 ints and N * (ns + 1) group offsets; the
+// through L2 instead).  Group (slice s, trial t) of the copy starts at
+// off[s * N + t] and holds cnt[s * N + t] ids (a multiple of 4, -1 padded);
+// the copy holds at most T + 3 * ns * N ids for T ids in the YET.  The
 // workspace holds each slice's per-trial partial sums and maxima.
 int32_t mean_slices(int32_t C);
 size_t mean_workspace_bytes(int32_t C, int64_t n_trials);
-hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStream_t s);
+hipError_t launch_yet_slice_count(const YetDev& y, uint32_t* cnt, hipStream_t s);
+hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, int32_t* ev2,
+                                    hipStream_t s);
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const int32_t* seg, void* ws, bool yelt, hipStream_t s);
+                       const int32_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
+                       hipStream_t s);
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
                          const LayerDev* layers, int32_t n_layers, int32_t wpb, hipStream_t s);
 

@@ -466,15 +466,32 @@ constexpr int kMeanTile = 1024;              // trials per workgroup
 constexpr int kLanesPerTrial = 16;           // lanes streaming one trial's group
 constexpr int kTrialsPerWave = 64 / kLanesPerTrial;
 
-// Start of trial t's regrouped ids: 16-byte aligned, with room for the
-// padding of every group.
-__device__ __forceinline__ int64_t sliced_base(int64_t row, int64_t t, int32_t ns)
+// The slice-major copy: group (slice s, trial t) holds trial t's ids that
+// fall in slice s, in time order, padded with -1 to a multiple of four; the
+// groups of one slice are consecutive over the trials, slice after slice, so
+// a workgroup streams one contiguous run.  k_yet_count sizes the groups,
+// an exclusive scan over (slice, trial) places them, k_yet_scatter fills them.
+__global__ __launch_bounds__(256) void k_yet_count(YetDev y, int32_t slice_len, int32_t ns, uint32_t* __restrict__ cnt)
 {
-    return ((row + 3) & ~(int64_t)3) + 4 * (int64_t)(ns + 1) * t;
+    const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= y.N) return;
+    const int lane = lane_id();
+    int64_t row;
+    int32_t len;
+    trial_range(y, t, row, len);
+    for (int32_t sl = 0; sl < ns; ++sl) {
+        int32_t c = 0;
+        for (int32_t k0 = 0; k0 < len; k0 += 64) {
+            const int32_t k = k0 + lane;
+            c += __popcll(__ballot(k < len && y.ev[row + k] / slice_len == sl));
+        }
+        if (lane == 0) cnt[(int64_t)sl * y.N + t] = (uint32_t)((c + 3) & ~3);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_yet_slice(YetDev y, int32_t slice_len, int32_t ns, int32_t* __restrict__ ev2,
-                                                   int32_t* __restrict__ seg)
+__global__ __launch_bounds__(256) void k_yet_scatter(YetDev y, int32_t slice_len, int32_t ns,
+                                                     const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ ev2)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= y.N) return;
@@ -483,44 +500,19 @@ __global__ __launch_bounds__(256) void k_yet_slice(YetDev y, int32_t slice_len, 
     int64_t row;
     int32_t len;
     trial_range(y, t, row, len);
-    const int64_t base = sliced_base(row, t, ns);
-    int32_t* sg = seg + t * (int64_t)(ns + 1);
-    // group sizes, padded to multiples of four, and their starts
-    int32_t st[kMaxSlices];
-    int32_t start = 0;
-#pragma unroll
-    for (int32_t sl = 0; sl < kMaxSlices; ++sl) {
-        st[sl] = start;
-        if (sl < ns) {
-            int32_t cnt = 0;
-            for (int32_t k0 = 0; k0 < len; k0 += 64) {
-                const int32_t k = k0 + lane;
-                const bool in = k < len && y.ev[row + k] / slice_len == sl;
-                cnt += __popcll(__ballot(in));
-            }
-            if (lane == 0) sg[sl] = start;
-            const int32_t padded = (cnt + 3) & ~3;
-            for (int32_t q = cnt + lane; q < padded; q += 64) ev2[base + start + q] = -1;
-            start += padded;
+    for (int32_t sl = 0; sl < ns; ++sl) {
+        const int64_t g = (int64_t)sl * y.N + t;
+        const int64_t start = off[g];
+        int32_t fill = 0;
+        for (int32_t k0 = 0; k0 < len; k0 += 64) {
+            const int32_t k = k0 + lane;
+            const int32_t id = k < len ? y.ev[row + k] : 0;
+            const bool mine = k < len && id / slice_len == sl;
+            const uint64_t m = __ballot(mine);
+            if (mine) ev2[start + fill + __popcll(m & below)] = id;
+            fill += __popcll(m);
         }
-    }
-    if (lane == 0) sg[ns] = start;
-    // scatter, keeping the time order inside each group
-    int32_t fill[kMaxSlices];
-#pragma unroll
-    for (int32_t sl = 0; sl < kMaxSlices; ++sl) fill[sl] = 0;
-    for (int32_t k0 = 0; k0 < len; k0 += 64) {
-        const int32_t k = k0 + lane;
-        const int32_t id = k < len ? y.ev[row + k] : 0;
-        const int32_t mine = k < len ? id / slice_len : -1;
-#pragma unroll
-        for (int32_t sl = 0; sl < kMaxSlices; ++sl) {
-            if (sl < ns) {
-                const uint64_t m = __ballot(mine == sl);
-                if (mine == sl) ev2[base + st[sl] + fill[sl] + __popcll(m & below)] = id;
-                fill[sl] += __popcll(m);
-            }
-        }
+        for (int32_t q = fill + lane; q < (int32_t)cnt[g]; q += 64) ev2[start + q] = -1;
     }
 }
 
@@ -530,7 +522,8 @@ __global__ __launch_bounds__(256) void k_yet_slice(YetDev y, int32_t slice_len, 
 __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_t t0, int64_t t1,
                                                                  const LayerDev* __restrict__ layers, int32_t l,
                                                                  const int32_t* __restrict__ ev2,
-                                                                 const int32_t* __restrict__ seg, int32_t slice_len,
+                                                                 const uint32_t* __restrict__ goff,
+                                                                 const uint32_t* __restrict__ gcnt, int32_t slice_len,
                                                                  int32_t ns, float2* __restrict__ part,
                                                                  float* __restrict__ pmax)
 {
@@ -558,12 +551,9 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
         at = 0;
         n4 = 0;
         if (i < te) {
-            const int64_t t = t0 + i;
-            const int64_t row = y.offs ? y.offs[t] : t * (int64_t)y.K;
-            const int32_t* sg = seg + t * (int64_t)(ns + 1);
-            const int32_t a = sg[sl], b = sg[sl + 1];
-            at = sliced_base(row, t, ns) + a;
-            n4 = (b - a) >> 2;
+            const int64_t g = (int64_t)sl * y.N + t0 + i;
+            at = goff[g];
+            n4 = (int32_t)(gcnt[g] >> 2);
         }
     };
     int64_t at_next;
@@ -941,16 +931,27 @@ size_t mean_workspace_bytes(int32_t C, int64_t n_trials)
     return (size_t)std::max<int32_t>(1, mean_slices(C)) * (size_t)n_trials * 12;
 }
 
-hipError_t launch_yet_slice(const YetDev& y, int32_t* ev2, int32_t* seg, hipStream_t s)
+hipError_t launch_yet_slice_count(const YetDev& y, uint32_t* cnt, hipStream_t s)
 {
     const int32_t ns = mean_slices(y.C);
     if (y.N <= 0 || ns == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_yet_slice, dim3(nblocks(y.N, 4)), dim3(256), 0, s, y, mean_slice_len(y.C), ns, ev2, seg);
+    hipLaunchKernelGGL(k_yet_count, dim3(nblocks(y.N, 4)), dim3(256), 0, s, y, mean_slice_len(y.C), ns, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, int32_t* ev2,
+                                    hipStream_t s)
+{
+    const int32_t ns = mean_slices(y.C);
+    if (y.N <= 0 || ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_yet_scatter, dim3(nblocks(y.N, 4)), dim3(256), 0, s, y, mean_slice_len(y.C), ns, off, cnt,
+                       ev2);
     return hipGetLastError();
 }
 
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const int32_t* seg, void* ws, bool yelt, hipStream_t s)
+                       const int32_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
+                       hipStream_t s)
 {
     const int64_t nt = t1 - t0;
     if (nt <= 0 || n_layers <= 0) return hipSuccess;
@@ -958,7 +959,7 @@ hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* 
         for (int32_t l = 0; l < n_layers; ++l)
             hipLaunchKernelGGL(k_mean_yelt, dim3(2048), dim3(256), 0, s, y, t0, t1, layers, l);
     const int32_t ns = mean_slices(y.C);
-    if (ns == 0) {
+    if (ns == 0 || !ev2) {
         hipLaunchKernelGGL(k_mean_gather, dim3(nblocks(nt, 4)), dim3(256), 0, s, y, t0, t1, layers, n_layers);
         return hipGetLastError();
     }
@@ -967,7 +968,7 @@ hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* 
     float* pmax = (float*)((char*)ws + (size_t)ns * nt * 8);
     for (int32_t l = 0; l < n_layers; ++l) {
         hipLaunchKernelGGL(k_mean_slice, dim3((unsigned)(n_tiles * ns)), dim3(64 * kMeanWaves), 0, s, y, t0, t1,
-                           layers, l, ev2, seg, mean_slice_len(y.C), ns, part, pmax);
+                           layers, l, ev2, goff, gcnt, mean_slice_len(y.C), ns, part, pmax);
         hipLaunchKernelGGL(k_mean_finish, dim3(nblocks(nt, 256)), dim3(256), 0, s, layers, l, nt, ns,
                            (const float2*)part, (const float*)pmax);
     }
