@@ -567,7 +567,7 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
         locate(i + kTrialsPerWave * kMeanWaves, at_next, n4_next);   // the next group's offsets, in flight early
         const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(ev2 + at);
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, m = 0.0f;
-#pragma unroll 4
+#pragma unroll 8
         for (int32_t q = sub; q < n4; q += kLanesPerTrial) {
             const v4i e = __builtin_nontemporal_load(v4 + q);
             const uint32_t u0 = (uint32_t)(e.x - lo), u1 = (uint32_t)(e.y - lo);
