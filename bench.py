@@ -37,11 +37,11 @@ PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 PEAK_VALU_TOPS = 157.3 / 2
 # VALU lane-instructions per draw of the plain layer kernel on this workload,
 # SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 1400.5
+VALU_OPS_PER_DRAW = 1401.4
 # Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2.0 * 26744469.0 + 1.0 * 3032423.8) * 1024
+TRAFFIC_BYTES = 8 * (2.0 * 28900434.1 + 1.0 * 5461966.8) * 1024
 
 
 def log(msg):
@@ -118,6 +118,7 @@ def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_st
         f"{marked}/{P.SUR_CELLS} cells fall back")
     if ckpt:
         P.save_surrogate(eng.ctx, ckpt)
+    tile = autotune(P, eng, yh, desc, P.MODE_SURROGATE, min(wl.n_trials, 100_000))["waves_per_workgroup"]
     step_s, kms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_SURROGATE, wl.seed, out, rps, steps, warmup)
     rel_p = np.abs(pml - plain_pml) / np.abs(plain_pml)
     rel_t = np.abs(tvar - plain_tvar) / np.abs(plain_tvar)
@@ -125,7 +126,7 @@ def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_st
             "speedup_vs_plain": plain_step_s / step_s, "pml": pml.tolist(), "tvar": tvar.tolist(),
             "pml_rel_diff_vs_plain": rel_p.tolist(), "tvar_rel_diff_vs_plain": rel_t.tolist(),
             "train": {"tuples": n_tuples, "epochs": epochs, "seconds": t_train, "final_mse": float(losses[-1])},
-            "fallback_cells": int(marked), "cells": P.SUR_CELLS,
+            "fallback_cells": int(marked), "cells": P.SUR_CELLS, "waves_per_workgroup": tile,
             "note": "PML/TVaR differences are against the plain GPU path, which matches the FP64 oracle per "
                     "trial far inside 1e-5 of the gross loss (tests/test_gpu_parity.py)"}
 
@@ -262,7 +263,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600)
     ap.add_argument("--serve-warmup", type=int, default=60)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget (0 = skip)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default trial tile (4 waves per workgroup)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default trial tile (1 wavefront per workgroup for the plain mode, 4 for the surrogate)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (FETCH_SIZE/WRITE_SIZE calibration under rocprofv3)")
     args = ap.parse_args()

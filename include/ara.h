@@ -180,7 +180,8 @@ ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *lay
 /*
  * Trial tile: the layer kernels evaluate one trial per 64-lane wavefront and
  * group `wpb` wavefronts (1, 2, 4 or 8; 8 not in surrogate mode) per
- * workgroup.  ara_set_trial_tile fixes it for a mode; ara_autotune times each
+ * workgroup (defaults: 1 for the plain mode, 4 for the surrogate mode).
+ * ara_set_trial_tile fixes it for a mode; ara_autotune times each
  * choice on the first n_trials trials for the given prepared layers (all of
  * one mode), keeps the fastest for that mode and returns it (ms_out,
  * optional: the time of each candidate 1, 2, 4, 8, float [4]).  Results do not

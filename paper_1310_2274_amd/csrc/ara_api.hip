@@ -93,7 +93,7 @@ struct ara_ctx {
     int64_t sur_step = 0;
     DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_bias, sur_loss;
     DevBuf sur_tuples, sur_gpart, sur_lpart, sur_calib;
-    int32_t wpb[3] = {4, 4, 4};     // trial tile (wavefronts per workgroup) per mode
+    int32_t wpb[3] = {4, 1, 4};     // trial tile (wavefronts per workgroup) per mode
     bool profiling = false;
     bool have_timing = false;
     hipEvent_t k_start = nullptr, k_stop = nullptr;
