@@ -375,6 +375,31 @@ __global__ void k_sur_entries(const EntryRec* __restrict__ pent, int64_t n, SurE
 // loss lands at its queue position, so the per-event sums keep the XELT order
 // and the result stays a function of the trial.
 // ===========================================================================
+// The exact inverse for the draws the surrogate does not answer, out of line
+// so its registers stay out of the MLP kernel's allocation.
+static __device__ __attribute__((noinline)) float exact_loss32(float z, EntryRec E)
+{
+    return E.maxl * inv_beta32(z, E);
+}
+static __device__ __attribute__((noinline)) float exact_loss64(double z, EntryRec E)
+{
+    return sample_loss(z, E);
+}
+// z of a draw; the correlated form (two normal quantiles and a CDF in FP64) out of line.
+static __device__ __attribute__((noinline)) double corr_draw_z(uint32_t trial, uint32_t slot, uint32_t j,
+                                                               uint32_t seed, uint32_t prog, const float2* pcw,
+                                                               uint32_t pi)
+{
+    return draw_z<true>(trial, slot, j, seed, prog, pcw, pi);
+}
+template <bool HAS_CORR>
+__device__ __forceinline__ double sur_draw_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed, uint32_t prog,
+                                             const float2* pcw, uint32_t pi)
+{
+    return HAS_CORR ? corr_draw_z(trial, slot, j, seed, prog, pcw, pi)
+                    : draw_z<false>(trial, slot, j, seed, prog, nullptr, pi);
+}
+
 constexpr int kSurRound = 8;
 constexpr int kSurQueue = 64 * kSurRound;
 
@@ -387,15 +412,14 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
 {
     __shared__ MlpFrag F;
     __shared__ uint32_t mask[kCells / 32];
-    __shared__ float bias[kCells];
     __shared__ uint32_t qidx[WPB][kSurQueue];
     __shared__ uint32_t qmeta[WPB][kSurQueue];
     __shared__ float qv[WPB][kSurQueue];
     __shared__ uint16_t lst[WPB][3][kSurQueue];
     copy_frag_to_lds(Fg, F);
     for (int w = threadIdx.x; w < kCells / 32; w += blockDim.x) mask[w] = gmask[w];
-    for (int w = threadIdx.x; w < kCells; w += blockDim.x) bias[w] = gbias[w];
     __syncthreads();
+    const float* __restrict__ bias = gbias;     // 16 KB, read through the L1 cache
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
@@ -450,7 +474,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const SurEntry SE = L.psur[pi];
                         if (SE.f0 >= flo && SE.f0 <= fhi && SE.f1 >= flo && SE.f1 <= fhi) {
-                            const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                            const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
                             const float v = normcdfinvf((float)z);
                             const int cell = sur_cell(SE.f0, SE.f1, v);
                             is_sur = !((mask[cell >> 5] >> (cell & 31)) & 1u);
@@ -498,8 +522,8 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
-                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                        const float loss = E.maxl * inv_beta32((float)z, E);
+                        const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        const float loss = exact_loss32((float)z, E);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);
                     }
@@ -512,8 +536,8 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
-                        const double z = draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                        const float loss = sample_loss(z, E);
+                        const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        const float loss = exact_loss64(z, E);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);
                     }
