@@ -40,7 +40,7 @@ struct EltRec {
     bool live = false;
     int32_t C = 0, n = 0;
     bool has_corr = false;
-    DevBuf idx, ent, cw, mean;
+    DevBuf idx, ent, cw, mean, sol;
     double ded = 0, lim = 0, share = 0;
 };
 
@@ -260,6 +260,7 @@ void plan_layer(const ara_layer_desc* L, const std::vector<const EltRec*>& es, L
         d.ent = (const EntryRec*)e.ent.p;
         d.cw = (const float2*)e.cw.p;
         d.mean = (const double*)e.mean.p;
+        d.solve = (const SolveRec*)e.sol.p;
         d.ded = e.ded;
         d.lim = e.lim;
         d.share = e.share;
@@ -285,6 +286,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
     size_t b = align256((size_t)C * 16) + 2 * align256((size_t)C * 4) + align256(scan_scratch_words(C) * 4) +
                align256(p.total * sizeof(EntryRec));
     if (p.has_corr) b += align256(p.total * 8);
+    if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
     return b;
 }
@@ -316,12 +318,18 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         pcw = (float2*)q;
         q += align256(p.total * 8);
     }
+    SolveRec* psol = nullptr;
+    if (mode == ARA_MODE_PLAIN) {
+        psol = (SolveRec*)q;
+        q += align256(p.total * sizeof(SolveRec));
+    }
     HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
     HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
-    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, s));
+    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, s));
     p.dev.rows = rows;
     p.dev.pent = pent;
     p.dev.pcw = pcw;
+    p.dev.psol = psol;
     if (mode == ARA_MODE_SURROGATE) {
         SurEntry* psur = (SurEntry*)q;
         q += align256(p.total * sizeof(SurEntry));
@@ -781,11 +789,13 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
             for (int32_t r = 0; r < d.n_entries && !e.has_corr; ++r) e.has_corr = d.sigma_c[r] > 0.0;
         const size_t n = (size_t)d.n_entries;
         if ((st = dev_alloc(c, e.idx, (size_t)C * 4)) || (st = dev_alloc(c, e.ent, n * sizeof(EntryRec))) ||
-            (st = dev_alloc(c, e.mean, n * 8)) || (e.has_corr && (st = dev_alloc(c, e.cw, n * 8)))) {
+            (st = dev_alloc(c, e.mean, n * 8)) || (e.has_corr && (st = dev_alloc(c, e.cw, n * 8))) ||
+            (st = dev_alloc(c, e.sol, n * sizeof(SolveRec)))) {
             dev_free(c, e.idx);
             dev_free(c, e.ent);
             dev_free(c, e.mean);
             dev_free(c, e.cw);
+            dev_free(c, e.sol);
             return st;
         }
         // raw inputs: ids, sigma_i, sigma_c, max (the mean goes straight to its own buffer)
@@ -807,6 +817,7 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
         HIPCHK(c, launch_elt_index(ids, d.n_entries, (int32_t*)e.idx.p, c->stream));
         HIPCHK(c, launch_elt_prepare(d.n_entries, (const double*)e.mean.p, si, d.sigma_c ? sc : nullptr, mx,
                                      (EntryRec*)e.ent.p, (float2*)e.cw.p, c->stream));
+        HIPCHK(c, launch_elt_solve(d.n_entries, (const EntryRec*)e.ent.p, (SolveRec*)e.sol.p, c->stream));
         // the staging buffer is reused by the next XELT: wait for this one
         HIPCHK(c, hipStreamSynchronize(c->stream));
         e.live = true;
@@ -828,6 +839,7 @@ ara_status ara_free_elts(ara_ctx* c, const int32_t* h, int32_t n)
         EltRec& e = c->elts[h[i]];
         dev_free(c, e.idx);
         dev_free(c, e.ent);
+        dev_free(c, e.sol);
         dev_free(c, e.cw);
         dev_free(c, e.mean);
         e.live = false;

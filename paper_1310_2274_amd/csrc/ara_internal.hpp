@@ -19,16 +19,25 @@ struct EltDev {
     const EntryRec* ent;    // [n] Beta parameters per entry
     const float2* cw;       // [n] (c_I, c_C) weights of section 3.2, or null if sigma_C == 0
     const double* mean;     // [n] mean loss mu_l
+    const SolveRec* solve;  // [n] FP32 solve records with their start tables
     double ded, lim, share; // financial terms I of the XELT
     int32_t n;
     int32_t pad;
 };
 
+// The fourth word of an event's row: the event's entry count in the layer
+// (bits 0-6) and, for its first kRowPolBits entries in rank order, whether the
+// entry takes the FP64 path (bit 7 + rank), so the solve can be chosen without
+// reading the entry.
+constexpr int kRowPolBits = 25;
+__host__ __device__ inline int row_count(uint32_t w) { return (int)(w & 127u); }
+
 // One layer of a run: its tables (built per run on the device) and terms.
 struct LayerDev {
-    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count}
+    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count | flags}
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
+    const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
     float* ylt;             // [trial_end - trial_begin]
@@ -55,12 +64,13 @@ struct YetDev {
 hipError_t launch_elt_index(const int32_t* event_id, int32_t n, int32_t* idx, hipStream_t s);
 hipError_t launch_elt_prepare(int32_t n, const double* mean, const double* sig_i, const double* sig_c,
                               const double* maxl, EntryRec* ent, float2* cw, hipStream_t s);
+hipError_t launch_elt_solve(int32_t n, const EntryRec* ent, SolveRec* sol, hipStream_t s);
 hipError_t launch_validate_ids(const int32_t* ev, int64_t n, int32_t C, unsigned int* bad, hipStream_t s);
 hipError_t launch_layer_count(int32_t C, int32_t J, const EltDev* elts, uint4* rows, uint32_t* cnt, hipStream_t s);
 size_t scan_scratch_words(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, hipStream_t s);
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, hipStream_t s);
+                             EntryRec* pent, float2* pcw, SolveRec* psol, hipStream_t s);
 hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,
                              float* occ_tab, hipStream_t s);
 // wpb: wavefronts (= trials) per workgroup, 1, 2, 4 or 8 -- the trial tile

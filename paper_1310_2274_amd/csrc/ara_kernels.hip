@@ -64,6 +64,14 @@ __global__ void k_elt_prepare(int32_t n, const double* __restrict__ mean, const 
     }
 }
 
+// Solve records with their start tables, one thread per entry, FP64.
+__global__ void k_elt_solve(int32_t n, const EntryRec* __restrict__ ent, SolveRec* __restrict__ sol)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    sol[r] = make_solve_rec(ent[r]);
+}
+
 __global__ void k_validate_ids(const int32_t* __restrict__ ev, int64_t n, int32_t C, unsigned int* bad)
 {
     unsigned int local = 0;
@@ -91,24 +99,30 @@ __global__ void k_layer_count(int32_t C, int32_t J, const EltDev* __restrict__ e
 }
 
 __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ elts, const uint32_t* __restrict__ off,
-                             uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw)
+                             uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw,
+                             SolveRec* __restrict__ psol)
 {
     const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= C) return;
     uint4 r = rows[e];
     uint32_t o = off[e];
     r.z = o;
-    rows[e] = r;
     uint64_t mask = (uint64_t)r.x | ((uint64_t)r.y << 32);
-    while (mask) {
+    uint32_t pol = 0;
+    for (int rank = 0; mask; ++rank) {
         const int j = __ffsll((unsigned long long)mask) - 1;
         mask &= mask - 1;
         const EltDev& X = elts[j];
         const int32_t i = X.idx[e];
-        pent[o] = X.ent[i];
+        const EntryRec E = X.ent[i];
+        pent[o] = E;
         if (pcw) pcw[o] = X.cw ? X.cw[i] : make_float2(1.0f, 0.0f);
+        if (psol) psol[o] = X.solve[i];
+        if (rank < kRowPolBits && needs_polish(E)) pol |= 1u << rank;
         ++o;
     }
+    r.w |= pol << 7;
+    rows[e] = r;
 }
 
 // Mean mode (primary uncertainty only): the loss of an event occurrence does
@@ -351,7 +365,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             if (valid) rr = L.rows[y.ev[row + k]];
             uint64_t mask = (uint64_t)rr.x | ((uint64_t)rr.y << 32);
             const uint32_t off = rr.z;
-            int remaining = (int)rr.w;
+            const uint32_t rw = rr.w;
+            int remaining = row_count(rw);
             int rank = 0;
             float c = 0.0f;                  // this event's loss across XELTs, deferred draws aside
             int pend = 0;                    // its deferred draws
@@ -364,8 +379,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 for (int i = 0; i < take; ++i) {
                     const int j = __ffsll((unsigned long long)mask) - 1;
                     mask &= mask - 1;
-                    QI[pos + i] = off + (uint32_t)(rank + i);
-                    QM[pos + i] = (uint16_t)(lane | (j << 8));
+                    const int rk = rank + i;
+                    const uint32_t pol = rk < kRowPolBits ? (rw >> (7 + rk)) & 1u : L.psol[off + (uint32_t)rk].pol;
+                    QI[pos + i] = off + (uint32_t)rk;
+                    QM[pos + i] = (uint16_t)(lane | (pol << 7) | (j << 8));
                 }
                 wave_sync();
                 // (A) classify: FP32 draws to the list, the others to the deferred ring
@@ -374,10 +391,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     const int q = b0 + lane;
                     const bool in = q < total;
                     bool pol = false;
-                    if (in) {
-                        const EntryRec& E = L.pent[QI[q]];
-                        pol = fmin(E.a, E.b) < kPolishShape;
-                    }
+                    if (in) pol = (QM[q] & 0x80u) != 0u;
                     const uint64_t b64 = __ballot(in && pol);
                     const uint64_t b32 = __ballot(in && !pol);
                     // correlated layers: the draw's z (two uniforms, normal transforms in
@@ -412,9 +426,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         const int q = L32[idx];
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
-                        const EntryRec E = L.pent[pi];
+                        const SolveRec& R = L.psol[pi];
                         const float z = HAS_CORR ? QV[q] : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
-                        const float loss = E.maxl * inv_beta32(z, E);
+                        const float loss = R.maxl * inv_beta32(z, R);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
                     }
@@ -804,7 +818,8 @@ __global__ void k_beta_quantile_layer(const double* __restrict__ a, const double
     E.lnB = log_beta(E.a, E.b);
     E.us = (float)beta_inc_lower((E.a + 1.0) / (E.a + E.b + 2.0), E.a, E.b, E.lnB);
     E.maxl = 1.0f;
-    x[i] = inv_beta_layer(u[i], E);
+    const SolveRec R = make_solve_rec(E);           // as the layer tables hold it
+    x[i] = inv_beta_layer(u[i], E, R);
 }
 
 // ===========================================================================
@@ -861,6 +876,12 @@ hipError_t launch_elt_prepare(int32_t n, const double* mean, const double* sig_i
     return hipGetLastError();
 }
 
+hipError_t launch_elt_solve(int32_t n, const EntryRec* ent, SolveRec* sol, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_elt_solve, dim3(nblocks(n, 64)), dim3(64), 0, s, n, ent, sol);
+    return hipGetLastError();
+}
+
 hipError_t launch_validate_ids(const int32_t* ev, int64_t n, int32_t C, unsigned int* bad, hipStream_t s)
 {
     if (n > 0) {
@@ -889,9 +910,9 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
 }
 
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, hipStream_t s)
+                             EntryRec* pent, float2* pcw, SolveRec* psol, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw);
+    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol);
     return hipGetLastError();
 }
 

@@ -274,40 +274,114 @@ __host__ __device__ inline bool needs_polish(const EntryRec& E)
     return (E.a < E.b ? E.a : E.b) < kPolishShape;
 }
 
-// FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape):
-// the same log-space Newton iteration as inv_beta's first stage, with the
-// hardware helpers above.  The loop stops once a step moves the quantile x by
-// less than 5e-4 relative: Newton's quadratic convergence then leaves a
-// relative error of order 1e-6 in x.  Device only.
-__device__ inline float inv_beta32(float z, const EntryRec& E)
+// ---------------------------------------------------------------------------
+// Per-entry start table of the FP32 solve.  On each side of t_s (the lower
+// side solves for t = x, the upper for t = 1 - x with the shapes swapped and
+// p = 1 - z) the solution y = ln t is written as the leading term plus a
+// residual, y = (ln p - c0)/A + r, where r vanishes as p -> 0.  r is tabulated
+// against u = (ln(p/p_s) / ln(p_min/p_s))^(1/3) in [0, 1] (p_s = I_{t_s} on
+// that side, p_min = 2^-24, the smallest p a draw takes) at the five knots
+// u_k = k/4, with its exact derivative (stored times the knot spacing h), for
+// cubic Hermite interpolation.  Built in FP64 from the solver itself and kept
+// in half precision: the interpolated start is within about 1e-3 of the root,
+// so one Newton step usually settles it and two nearly always do.
+// ---------------------------------------------------------------------------
+constexpr int kKnots = 5;
+constexpr float kLnPmin = -16.635532333438686f;      // ln 2^-24
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+// One entry's record for the FP32 solve: the shapes and constants in FP32 and
+// both sides' start tables, one 64-byte line per draw.
+struct alignas(64) SolveRec {
+    float a, b;                   // alpha, beta
+    float lnB;                    // ln B(alpha, beta)
+    float us;                     // I_ts, as in EntryRec
+    float maxl;                   // max_l
+    uint32_t pol;                 // 1: the draw takes the FP64 path (needs_polish), no table
+    half2_t knot[2][kKnots];      // side 0 lower, 1 upper: (r_k, h * dr/du at u_k)
+};
+static_assert(sizeof(SolveRec) == 64, "SolveRec must stay one 64-byte line");
+
+// Knots of one side, out[2k] = r_k and out[2k+1] = h * dr/du at u_k.  A side
+// no draw reaches, or one whose knots leave FP64 range, is left zero (the
+// start is then the leading term alone).
+__host__ __device__ inline void knot_side(const EntryRec& E, bool lower, float* out)
 {
-    const bool lower = z <= E.us;
-    const float A = (float)(lower ? E.a : E.b);
-    const float B = (float)(lower ? E.b : E.a);
-    const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
-    const float lnp = f32_ln(p);
-    const float rA = f32_rcp(A);
-    const float c0 = -((float)E.lnB + f32_ln(A));
-    const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
-    const float lts = f32_ln(ts);
-    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
-    // Start: ln I_t = A y + c0 + g(t) with g(t) = B ln(1-t) - ln T(t), which
-    // vanishes at t = 0 and equals ln I_ts - A ln ts - c0 at ts (I_ts is
-    // stored).  Taking g linear in t and evaluating it at the leading-term
-    // root gives one cheap fixed-point step that brings the draws near ts,
-    // where the leading term alone is worst, within one Newton step.
-    float y = fminf((lnp - c0) * rA, lts);
-    const float gs = f32_ln(lower ? E.us : 1.0f - E.us) - A * lts - c0;
-    y = fminf((lnp - c0 - gs * __expf(y) * f32_rcp(ts)) * rA, lts);
+    for (int k = 0; k < 2 * kKnots; ++k) out[k] = 0.0f;
+    if (E.a == 0.0) return;                                // degenerate entry: no draws solve
+    const double A = lower ? E.a : E.b, B = lower ? E.b : E.a;
+    const double ps = lower ? (double)E.us : 1.0 - (double)E.us;
+    if (!(ps > 0.0)) return;
+    const double lnps = log(ps);
+    const double smin = (double)kLnPmin - lnps;
+    if (!(smin < 0.0)) return;                             // no p on the 2^-24 grid reaches this side
+    const double c0 = -(E.lnB + log(A));
+    const double h = 1.0 / (kKnots - 1);
+    EntryRec S = E;                                        // the side's own problem: shapes (A, B), I_ts = p_s
+    S.a = A;
+    S.b = B;
+    S.us = (float)ps;
+    const double ts = (A + 1.0) / (A + B + 2.0);
+    for (int k = 0; k < kKnots; ++k) {
+        const double u = k * h;
+        const double sk = smin * u * u * u;
+        const double p = ps * exp(sk);
+        const double t = (k == 0) ? ts : inv_beta(p, S);
+        if (!(t > 0.0)) {                                  // below FP64 range: leave the side empty
+            for (int q = 0; q < 2 * kKnots; ++q) out[q] = 0.0f;
+            return;
+        }
+        double num, den;
+        beta_cf<double>(t, A, B, 1e-15, 400, num, den);
+        const double dyds = (1.0 - t) * den / (A * num);   // 1 / (d ln I / d ln t)
+        out[2 * k] = (float)(log(t) - (log(p) - c0) / A);
+        out[2 * k + 1] = (float)((dyds - 1.0 / A) * smin * 3.0 * u * u * h);
+    }
+}
+
+__host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
+{
+    SolveRec R;
+    R.a = (float)E.a;
+    R.b = (float)E.b;
+    R.lnB = (float)E.lnB;
+    R.us = E.us;
+    R.maxl = E.maxl;
+    R.pol = needs_polish(E) ? 1u : 0u;
+    for (int side = 0; side < 2; ++side) {
+        float v[2 * kKnots];
+        if (R.pol) {
+            for (int k = 0; k < 2 * kKnots; ++k) v[k] = 0.0f;
+        } else {
+            knot_side(E, side == 0, v);
+        }
+        for (int k = 0; k < kKnots; ++k) {
+            half2_t q;
+            q.x = (_Float16)v[2 * k];
+            q.y = (_Float16)v[2 * k + 1];
+            R.knot[side][k] = q;
+        }
+    }
+    return R;
+}
+
+// Newton iteration of the FP32 solve from the start y.  From a rough start
+// (ROUGH) the first step only has to land near the root: a continued fraction
+// good to 1e-2 suffices there, and that step never ends the loop.  The loop
+// stops once a step moves the quantile x by less than 5e-4 relative: Newton's
+// quadratic convergence then leaves a relative error of order 1e-6 in x.
+template <bool ROUGH>
+__device__ inline float newton32(float y, bool lower, float A, float B, float lnp, float c0, float rA, float ymax)
+{
     const float yfloor = lower ? -110.0f : -40.0f;
     for (int it = 0; it < 10 && y > yfloor; ++it) {
         const float t = __expf(y);
         const float w = 1.0f - t;
         const float l1t = f32_log1m(t, w);
         float num, den;
-        // the first step only has to land near the root: a fraction good to 1e-2
-        // suffices there, and that step never ends the loop
-        beta_cf<float>(t, A, B, it == 0 ? 1e-2f : 2e-7f, 48, num, den);
+        const bool rough = ROUGH && it == 0;
+        beta_cf<float>(t, A, B, rough ? 1e-2f : 2e-7f, 48, num, den);
         const float rnum = f32_rcp(num);
         const float f = A * y + B * l1t + c0 + f32_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
         const float dy = -(f * w * den) * (rA * rnum);
@@ -316,16 +390,69 @@ __device__ inline float inv_beta32(float z, const EntryRec& E)
         y = yn;
         // a step dy moves x by dy (lower side, x = t) or by dy * t / (1 - t)
         // relative to x (upper side, x = 1 - t)
-        if (it > 0 && fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
+        if (!rough && fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
     }
     return lower ? __expf(y) : -expm1f(y);
 }
 
-// The inverse the plain layer kernel applies to one draw.
-__device__ inline double inv_beta_layer(double z, const EntryRec& E)
+// FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape),
+// started from the entry's table: the log-space Newton iteration of inv_beta's
+// first stage with the hardware helpers above.  Device only.
+__device__ inline float inv_beta32(float z, const SolveRec& R)
 {
-    if (needs_polish(E)) return inv_beta(z, E);
-    return (double)inv_beta32((float)z, E);
+    const bool lower = z <= R.us;
+    const float A = lower ? R.a : R.b;
+    const float B = lower ? R.b : R.a;
+    const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
+    const float lnp = f32_ln(p);
+    const float rA = f32_rcp(A);
+    const float c0 = -(R.lnB + f32_ln(A));
+    const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    const float lnps = f32_ln(lower ? R.us : 1.0f - R.us);
+    // the tabulated residual at u, cubic Hermite between the two knots around it
+    const half2_t* K = R.knot[lower ? 0 : 1];
+    const float q = fmaxf((lnp - lnps) * f32_rcp(kLnPmin - lnps), 0.0f);
+    const float u = fminf(exp2f(__builtin_amdgcn_logf(q) * (1.0f / 3.0f)), 1.0f);   // q^(1/3)
+    const float g = u * (float)(kKnots - 1);
+    const int j = min((int)g, kKnots - 2);
+    const float w = g - (float)j, w1 = 1.0f - w;
+    const half2_t k0 = K[j], k1 = K[j + 1];
+    const float r = (1.0f + 2.0f * w) * w1 * w1 * (float)k0.x + w * w1 * w1 * (float)k0.y +
+                    w * w * (3.0f - 2.0f * w) * (float)k1.x - w * w * w1 * (float)k1.y;
+    return newton32<false>(fminf((lnp - c0) * rA + r, ymax), lower, A, B, lnp, c0, rA, ymax);
+}
+
+// The same solve started from a corrected leading term, for callers that hold
+// only the entry record.  ln I_t = A y + c0 + g(t) with g(t) = B ln(1-t) -
+// ln T(t), which vanishes at t = 0 and equals ln I_ts - A ln ts - c0 at ts (I_ts
+// is stored).  Taking g linear in t and evaluating it at the leading-term root
+// gives one cheap fixed-point step that brings the draws near ts, where the
+// leading term alone is worst, within one Newton step.  Device only.
+__device__ inline float inv_beta32(float z, const EntryRec& E)
+{
+    const bool lower = z <= E.us;
+    const float A = (float)(lower ? E.a : E.b);
+    const float B = (float)(lower ? E.b : E.a);
+    const float p = lower ? z : 1.0f - z;
+    const float lnp = f32_ln(p);
+    const float rA = f32_rcp(A);
+    const float c0 = -((float)E.lnB + f32_ln(A));
+    const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
+    const float lts = f32_ln(ts);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    const float lnps = f32_ln(lower ? E.us : 1.0f - E.us);
+    float y = fminf((lnp - c0) * rA, lts);
+    const float gs = lnps - A * lts - c0;
+    y = fminf((lnp - c0 - gs * __expf(y) * f32_rcp(ts)) * rA, lts);
+    return newton32<true>(y, lower, A, B, lnp, c0, rA, ymax);
+}
+
+// The inverse the plain layer kernel applies to one draw.
+__device__ inline double inv_beta_layer(double z, const EntryRec& E, const SolveRec& R)
+{
+    if (R.pol) return inv_beta(z, E);
+    return (double)inv_beta32((float)z, R);
 }
 
 // Sampled loss of one draw: max_l * InvCDF_beta(z; alpha, beta) (section 3.3).

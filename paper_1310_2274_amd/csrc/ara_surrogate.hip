@@ -447,7 +447,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
             if (valid) r = L.rows[y.ev[row + k]];
             uint64_t msk = (uint64_t)r.x | ((uint64_t)r.y << 32);
             const uint32_t off = r.z;
-            int remaining = (int)r.w;
+            int remaining = row_count(r.w);
             int rank = 0;
             float c = 0.0f;
             while (true) {
