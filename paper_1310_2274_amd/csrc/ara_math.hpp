@@ -283,8 +283,8 @@ __host__ __device__ inline bool needs_polish(const EntryRec& E)
 // that side, p_min = 2^-24, the smallest p a draw takes) at the five knots
 // u_k = k/4, with its exact derivative (stored times the knot spacing h), for
 // cubic Hermite interpolation.  Built in FP64 from the solver itself and kept
-// in half precision: the interpolated start is within about 1e-3 of the root,
-// so one Newton step usually settles it and two nearly always do.
+// in half precision: the interpolated start is within about 1e-3 of the root
+// (1e-2 at worst), so one Halley step settles all but about 1.5% of draws.
 // ---------------------------------------------------------------------------
 constexpr int kKnots = 5;
 constexpr float kLnPmin = -16.635532333438686f;      // ln 2^-24
@@ -366,11 +366,18 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
     return R;
 }
 
-// Newton iteration of the FP32 solve from the start y.  From a rough start
-// (ROUGH) the first step only has to land near the root: a continued fraction
-// good to 1e-2 suffices there, and that step never ends the loop.  The loop
-// stops once a step moves the quantile x by less than 5e-4 relative: Newton's
-// quadratic convergence then leaves a relative error of order 1e-6 in x.
+// Halley iteration of the FP32 solve from the start y, on f(y) = ln I_t - ln p
+// with t = e^y.  f'(y) = 1/(dy/d ln I) is what the Newton step divides by, and
+// f''/f' = A - (B-1) t/(1-t) - f', so the cubic correction costs a few
+// operations: with the Newton step d = -f/f', Halley's step is
+// d / (1 + d f''/(2 f')), taken while that factor stays within (1/2, 3/2).
+// From a rough start (ROUGH) the first step only has to land near the root: a
+// continued fraction good to 1e-2 suffices there, and that step never ends the
+// loop.  The loop stops once a step moves the quantile x by less than 2e-2
+// relative: cubic convergence then leaves an error of a few 1e-6 in x on the
+// shapes this path takes (min(a, b) >= kPolishShape), against the FP64 inverse.
+constexpr float kStopX = 2e-2f;
+
 template <bool ROUGH>
 __device__ inline float newton32(float y, bool lower, float A, float B, float lnp, float c0, float rA, float ymax)
 {
@@ -379,25 +386,28 @@ __device__ inline float newton32(float y, bool lower, float A, float B, float ln
         const float t = __expf(y);
         const float w = 1.0f - t;
         const float l1t = f32_log1m(t, w);
+        const float tw = t * f32_rcp(w);
         float num, den;
         const bool rough = ROUGH && it == 0;
         beta_cf<float>(t, A, B, rough ? 1e-2f : 2e-7f, 48, num, den);
         const float rnum = f32_rcp(num);
         const float f = A * y + B * l1t + c0 + f32_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
-        const float dy = -(f * w * den) * (rA * rnum);
+        float dy = -(f * w * den) * (rA * rnum);                           // Newton: -f/f'
+        const float hc = 0.5f * ((A - (B - 1.0f) * tw) * dy + f);          // d f''/(2 f')
+        if (fabsf(hc) < 0.5f) dy *= f32_rcp(1.0f + hc);
         const float yn = fminf(y + dy, ymax);
         const float step = yn - y;
         y = yn;
         // a step dy moves x by dy (lower side, x = t) or by dy * t / (1 - t)
         // relative to x (upper side, x = 1 - t)
-        if (!rough && fabsf(step) * (lower ? 1.0f : t * f32_rcp(w)) <= 5e-4f) break;
+        if (!rough && fabsf(step) * (lower ? 1.0f : tw) <= kStopX) break;
     }
     return lower ? __expf(y) : -expm1f(y);
 }
 
 // FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape),
-// started from the entry's table: the log-space Newton iteration of inv_beta's
-// first stage with the hardware helpers above.  Device only.
+// started from the entry's table: inv_beta's log-space iteration with Halley's
+// correction and the hardware helpers above.  Device only.
 __device__ inline float inv_beta32(float z, const SolveRec& R)
 {
     const bool lower = z <= R.us;
