@@ -193,6 +193,17 @@ __host__ __device__ inline float f32_rcp(float x)
     return 1.0f / x;
 #endif
 }
+// e with x = m 2^e, 1/2 <= |m| < 1 (0 for x = 0)
+__host__ __device__ inline int f32_frexp_exp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_frexp_expf(x);
+#else
+    int e;
+    frexpf(x, &e);
+    return e;
+#endif
+}
 // ln(1 - t) for 0 <= t < 1: with w = fl(1 - t), ln(w) * t / (1 - w) corrects
 // the rounding of w (Goldberg's log1p), a few ulps without extended precision.
 __host__ __device__ inline float f32_log1m(float t, float w)
@@ -279,15 +290,23 @@ __host__ __device__ inline bool needs_polish(const EntryRec& E)
 // side solves for t = x, the upper for t = 1 - x with the shapes swapped and
 // p = 1 - z) the solution y = ln t is written as the leading term plus a
 // residual, y = (ln p - c0)/A + r, where r vanishes as p -> 0.  r is tabulated
-// against u = (ln(p/p_s) / ln(p_min/p_s))^(1/3) in [0, 1] (p_s = I_{t_s} on
-// that side, p_min = 2^-24, the smallest p a draw takes) at the five knots
-// u_k = k/4, with its exact derivative (stored times the knot spacing h), for
-// cubic Hermite interpolation.  Built in FP64 from the solver itself and kept
-// in half precision: the interpolated start is within about 1e-3 of the root
-// (1e-2 at worst), so one Halley step settles all but about 1.5% of draws.
+// at five knots u_k = k/4 of a variable u in [0, 1], with its exact
+// derivative (stored times the knot spacing h), for cubic Hermite
+// interpolation.  The variable depends on the side's leading shape A:
+//  * A < kVmapShape: u = (p/p_s)^(1/A) (p_s = I_{t_s} on that side).  The
+//    series of I_t about t = 0 makes r a power series in t0 u (t0 the leading
+//    term's root at p_s), so r is smooth in u from u = 0, where it vanishes
+//    with slope (B-1)/(A+1) t0;
+//  * otherwise u = (ln(p/p_s) / ln(p_min/p_s))^(1/3) (p_min = 2^-24, the
+//    smallest p a draw takes): for large A the draws crowd towards t_s, where
+//    the first variable would pile them up at u = 1.
+// Built in FP64 from the solver itself and kept in half precision: the
+// interpolated start is within about 1e-3 of the root (1e-2 at worst), so one
+// Halley step settles nearly every draw.
 // ---------------------------------------------------------------------------
 constexpr int kKnots = 5;
 constexpr float kLnPmin = -16.635532333438686f;      // ln 2^-24
+constexpr float kVmapShape = 3.0f;
 
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
@@ -318,6 +337,7 @@ __host__ __device__ inline void knot_side(const EntryRec& E, bool lower, float* 
     if (!(smin < 0.0)) return;                             // no p on the 2^-24 grid reaches this side
     const double c0 = -(E.lnB + log(A));
     const double h = 1.0 / (kKnots - 1);
+    const bool vmap = (float)A < kVmapShape;               // the same test the solve makes
     EntryRec S = E;                                        // the side's own problem: shapes (A, B), I_ts = p_s
     S.a = A;
     S.b = B;
@@ -325,18 +345,33 @@ __host__ __device__ inline void knot_side(const EntryRec& E, bool lower, float* 
     const double ts = (A + 1.0) / (A + B + 2.0);
     for (int k = 0; k < kKnots; ++k) {
         const double u = k * h;
-        const double sk = smin * u * u * u;
-        const double p = ps * exp(sk);
-        const double t = (k == 0) ? ts : inv_beta(p, S);
-        if (!(t > 0.0)) {                                  // below FP64 range: leave the side empty
+        double r, d;
+        if (vmap && k == 0) {
+            r = 0.0;
+            d = (B - 1.0) / (A + 1.0) * exp((lnps - c0) / A);
+        } else {
+            // ln(p/p_s) at the knot, and d ln(p/p_s)/du there
+            const double sk = vmap ? A * log(u) : smin * u * u * u;
+            const double dsdu = vmap ? A / u : smin * 3.0 * u * u;
+            const double p = (k == kKnots - 1 && vmap) || (k == 0) ? ps : ps * exp(sk);
+            const double t = (p == ps) ? ts : inv_beta(p, S);
+            if (!(t > 0.0)) {                              // below FP64 range: leave the side empty
+                for (int q = 0; q < 2 * kKnots; ++q) out[q] = 0.0f;
+                return;
+            }
+            double num, den;
+            beta_cf<double>(t, A, B, 1e-15, 400, num, den);
+            const double dyds = (1.0 - t) * den / (A * num);   // 1 / (d ln I / d ln t)
+            r = log(t) - (log(p) - c0) / A;
+            d = (dyds - 1.0 / A) * dsdu;
+        }
+        if (!(fabs(r) < 1e4)) {                            // beyond half precision: no table
             for (int q = 0; q < 2 * kKnots; ++q) out[q] = 0.0f;
             return;
         }
-        double num, den;
-        beta_cf<double>(t, A, B, 1e-15, 400, num, den);
-        const double dyds = (1.0 - t) * den / (A * num);   // 1 / (d ln I / d ln t)
-        out[2 * k] = (float)(log(t) - (log(p) - c0) / A);
-        out[2 * k + 1] = (float)((dyds - 1.0 / A) * smin * 3.0 * u * u * h);
+        if (!(fabs(d) < 1e4)) d = 0.0;
+        out[2 * k] = (float)r;
+        out[2 * k + 1] = (float)(d * h);
     }
 }
 
@@ -366,6 +401,46 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
     return R;
 }
 
+// The continued fraction F = 1/(1 + d1/(1 + d2/(1 + ...))) of DLMF 8.17.22
+// in FP32 (I_t = t^A (1-t)^B / (A B(A, B)) F), as the ratio P/Q of the
+// continuants of that normalized form (every partial denominator 1):
+//   X_n = X_{n-1} + d_n X_{n-2},
+//   d_{2m+1} = -(A+m)(A+B+m) t / ((A+2m)(A+2m+1)),
+//   d_{2m+2} = (m+1)(B-m-1) t / ((A+2m+1)(A+2m+2)).
+// The continuants stay near order one, so a power-of-two rescale every two
+// pairs of terms keeps them in range; the two denominators of a pair share
+// one reciprocal.  Convergence (successive approximants within eps) is tested
+// after every two pairs; at most 48 pairs.
+__host__ __device__ inline void beta_cf32(float t, float A, float B, float eps, float& P, float& Q)
+{
+    float P2 = 0.0f, P1 = 1.0f, Q2 = 1.0f, Q1 = 1.0f;     // X_{n-2}, X_{n-1} from n = 2
+    const float apb = A + B, bm1 = B - 1.0f;
+    float fm = 0.0f;                                      // m, carried as a float
+    for (int k = 0; k < 24; ++k) {
+        for (int h = 0; h < 2; ++h, fm += 1.0f) {
+            const float a2 = fmaf(2.0f, fm, A), a21 = a2 + 1.0f;
+            const float Do = a2 * a21, De = a21 * (a2 + 2.0f);
+            const float r = f32_rcp(Do * De);
+            const float d_o = -(A + fm) * (apb + fm) * t * (De * r);
+            const float d_e = (fm + 1.0f) * (bm1 - fm) * t * (Do * r);
+            const float Po = fmaf(d_o, P2, P1), Qo = fmaf(d_o, Q2, Q1);
+            P1 = fmaf(d_e, P1, Po);
+            Q1 = fmaf(d_e, Q1, Qo);
+            P2 = Po;
+            Q2 = Qo;
+        }
+        const int ex = -f32_frexp_exp(Q1);
+        P2 = ldexpf(P2, ex);
+        Q2 = ldexpf(Q2, ex);
+        P1 = ldexpf(P1, ex);
+        Q1 = ldexpf(Q1, ex);
+        const float x = P1 * Q2;
+        if (fabsf(x - P2 * Q1) <= eps * fabsf(x)) break;
+    }
+    P = P1;
+    Q = Q1;
+}
+
 // Halley iteration of the FP32 solve from the start y, on f(y) = ln I_t - ln p
 // with t = e^y.  f'(y) = 1/(dy/d ln I) is what the Newton step divides by, and
 // f''/f' = A - (B-1) t/(1-t) - f', so the cubic correction costs a few
@@ -373,10 +448,10 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
 // d / (1 + d f''/(2 f')), taken while that factor stays within (1/2, 3/2).
 // From a rough start (ROUGH) the first step only has to land near the root: a
 // continued fraction good to 1e-2 suffices there, and that step never ends the
-// loop.  The loop stops once a step moves the quantile x by less than 2e-2
+// loop.  The loop stops once a step moves the quantile x by less than 1e-2
 // relative: cubic convergence then leaves an error of a few 1e-6 in x on the
 // shapes this path takes (min(a, b) >= kPolishShape), against the FP64 inverse.
-constexpr float kStopX = 2e-2f;
+constexpr float kStopX = 1e-2f;
 
 template <bool ROUGH>
 __device__ inline float newton32(float y, bool lower, float A, float B, float lnp, float c0, float rA, float ymax)
@@ -387,12 +462,12 @@ __device__ inline float newton32(float y, bool lower, float A, float B, float ln
         const float w = 1.0f - t;
         const float l1t = f32_log1m(t, w);
         const float tw = t * f32_rcp(w);
-        float num, den;
+        float P, Q;
         const bool rough = ROUGH && it == 0;
-        beta_cf<float>(t, A, B, rough ? 1e-2f : 2e-7f, 48, num, den);
-        const float rnum = f32_rcp(num);
-        const float f = A * y + B * l1t + c0 + f32_ln(den * rnum) - lnp;   // ln(1/T) = ln(den/num)
-        float dy = -(f * w * den) * (rA * rnum);                           // Newton: -f/f'
+        beta_cf32(t, A, B, rough ? 1e-2f : 2e-7f, P, Q);
+        const float F = P * f32_rcp(Q);
+        const float f = A * y + B * l1t + c0 + f32_ln(F) - lnp;
+        float dy = -(f * w * F) * rA;                                      // Newton: -f/f', f' = A/((1-t) F)
         const float hc = 0.5f * ((A - (B - 1.0f) * tw) * dy + f);          // d f''/(2 f')
         if (fabsf(hc) < 0.5f) dy *= f32_rcp(1.0f + hc);
         const float yn = fminf(y + dy, ymax);
@@ -423,7 +498,9 @@ __device__ inline float inv_beta32(float z, const SolveRec& R)
     // the tabulated residual at u, cubic Hermite between the two knots around it
     const half2_t* K = R.knot[lower ? 0 : 1];
     const float q = fmaxf((lnp - lnps) * f32_rcp(kLnPmin - lnps), 0.0f);
-    const float u = fminf(exp2f(__builtin_amdgcn_logf(q) * (1.0f / 3.0f)), 1.0f);   // q^(1/3)
+    const float u = fminf(A < kVmapShape ? f32_exp((lnp - lnps) * rA)                    // (p/p_s)^(1/A)
+                                         : exp2f(__builtin_amdgcn_logf(q) * (1.0f / 3.0f)),   // q^(1/3)
+                          1.0f);
     const float g = u * (float)(kKnots - 1);
     const int j = min((int)g, kKnots - 2);
     const float w = g - (float)j, w1 = 1.0f - w;
