@@ -213,9 +213,10 @@ constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 // The FP64 polish of a deferred draw, out of line: a call whose registers
 // stay out of the layer kernel's allocation (inlined, they force spills in
 // the kernel's hot loops at five wavefronts per SIMD).
-__device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E)
+__device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E, const SolveRec* R)
 {
-    return sample_loss(z, E);
+    if (E.a == 0.0) return (float)E.lnB;       // degenerate: the mean loss
+    return E.maxl * (float)inv_beta(z, E, nullptr, R);
 }
 
 // The correlated draw's z (two uniforms, two FP64 normal quantiles, one
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 key = meta & 0xFFFFFFu;
                 const EntryRec E = L.pent[pi];
                 const double z = HAS_CORR ? DZ[e] : draw_z<false>(tr, key, j, L.seed, L.prog, nullptr, pi);
-                const float loss = polish_loss(z, E);
+                const float loss = polish_loss(z, E, L.psol + pi);
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
             }

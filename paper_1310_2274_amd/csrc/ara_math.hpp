@@ -158,10 +158,12 @@ __host__ __device__ inline double beta_inc_lower(double t, double A, double B, d
 //   f'(y) = A T / (1 - t),
 // which is close to linear in the tails (I ~ t^A / (A B)), so Newton's method
 // converges in a few steps from the leading-term start y0 = (ln p + ln A +
-// lnB)/A even for shape parameters of 1e-6.  An FP32 stage brings y within
-// ~1e-3, then FP64 steps finish it (quadratic convergence): the FP64 pass is
-// what keeps tiny shapes, whose quantile amplifies any error in ln I by 1/A,
-// accurate to well below the YLT tolerance.
+// lnB)/A even for shape parameters of 1e-6.  Both stages take Halley's steps
+// (the second derivative costs a few operations in this form, see newton32).
+// An FP32 stage brings y within ~1e-3, then FP64 steps finish it (cubic
+// convergence, one step nearly always): the FP64 pass is what keeps tiny
+// shapes, whose quantile amplifies any error in ln I by 1/A, accurate to well
+// below the YLT tolerance.
 // ---------------------------------------------------------------------------
 struct InvBetaStats {
     int it32, it64;
@@ -211,80 +213,6 @@ __host__ __device__ inline float f32_log1m(float t, float w)
     return (w == 1.0f) ? -t : f32_ln(w) * (t * f32_rcp(1.0f - w));
 }
 
-__host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaStats* st = nullptr)
-{
-    const bool lower = z <= (double)E.us;
-    const double A = lower ? E.a : E.b;
-    const double B = lower ? E.b : E.a;
-    const double p = lower ? z : 1.0 - z;
-    const double lnB = E.lnB;
-
-    // ---- FP32 stage
-    const float Af = (float)A, Bf = (float)B;
-    const float lnpf = f32_ln((float)p);
-    const float rA = f32_rcp(Af);
-    const float ts = (Af + 1.0f) * f32_rcp(Af + Bf + 2.0f);
-    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
-    // the leading term and the constants are formed in FP64: for tiny A the
-    // two logs cancel to O(A) and the FP32 difference would be noise
-    const float c0f = (float)(-(lnB + log(A)));
-    float y = (float)((log(p) + log(A) + lnB) / A);
-    y = fmaxf(fminf(y, f32_ln(ts)), -1e30f);
-    // below these t the loss rounds to 0 (lower side, FP32 loss) or x to 1
-    // (upper side, FP64): no need to iterate further
-    const float yfloor = lower ? -110.0f : -40.0f;
-    int it32 = 0;
-    for (; it32 < 12 && y > yfloor; ++it32) {
-        const float t = f32_exp(y);
-        const float w = 1.0f - t;
-        const float l1t = f32_log1m(t, w);
-        float num, den;
-        beta_cf<float>(t, Af, Bf, 2e-7f, 48, num, den);
-        const float rnum = f32_rcp(num);
-        const float f = Af * y + Bf * l1t + c0f + f32_ln(den * rnum) - lnpf;   // ln(1/T) = ln(den/num)
-        const float dy = -(f * w * den) * (rA * rnum);
-        const float yn = fmaxf(fminf(y + dy, ymax), -1e30f);
-        const float step = yn - y;
-        y = yn;
-        if (fabsf(step) <= 2e-3f * fmaxf(1.0f, fabsf(y))) break;
-    }
-
-    // ---- FP64 polish
-    const double lnA = log(A), lnp = log(p);
-    const double ts64 = (A + 1.0) / (A + B + 2.0);
-    const double ymax64 = log(fmin(1.1 * ts64, 0.5 * (1.0 + ts64)));
-    double yd = (double)y;
-    int it64 = 0;
-    for (; it64 < 6 && yd > (double)yfloor; ++it64) {
-        const double t = exp(yd);
-        const double l1t = log1p(-t);
-        double num, den;
-        beta_cf<double>(t, A, B, 1e-15, 200, num, den);
-        const double T = num / den;
-        const double f = A * yd + B * l1t - lnB - lnA - log(T) - lnp;
-        const double dy = -f * (1.0 - t) / (A * T);
-        const double yn = fmax(fmin(yd + dy, ymax64), -1e300);
-        const double step = yn - yd;
-        yd = yn;
-        if (fabs(step) <= 1e-5) break;
-    }
-    if (st) {
-        st->it32 = it32;
-        st->it64 = it64;
-    }
-    return lower ? exp(yd) : -expm1(yd);
-}
-
-// Draws whose smaller shape parameter is below this take the FP64 polish; at
-// or above it the FP32 solve alone is accurate to a few 1e-6 relative (the
-// quantile's sensitivity to an error in ln I grows like 1/shape).
-constexpr double kPolishShape = 0.2;
-
-__host__ __device__ inline bool needs_polish(const EntryRec& E)
-{
-    return (E.a < E.b ? E.a : E.b) < kPolishShape;
-}
-
 // ---------------------------------------------------------------------------
 // Per-entry start table of the FP32 solve.  On each side of t_s (the lower
 // side solves for t = x, the upper for t = 1 - x with the shapes swapped and
@@ -311,16 +239,118 @@ constexpr float kVmapShape = 3.0f;
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 // One entry's record for the FP32 solve: the shapes and constants in FP32 and
-// both sides' start tables, one 64-byte line per draw.
+// both sides' start tables, one 64-byte line per draw.  Entries that take the
+// FP64 path (pol) carry tables too: they start its FP32 stage.
 struct alignas(64) SolveRec {
     float a, b;                   // alpha, beta
     float lnB;                    // ln B(alpha, beta)
     float us;                     // I_ts, as in EntryRec
     float maxl;                   // max_l
-    uint32_t pol;                 // 1: the draw takes the FP64 path (needs_polish), no table
+    uint32_t pol;                 // 1: the draw takes the FP64 path (needs_polish)
     half2_t knot[2][kKnots];      // side 0 lower, 1 upper: (r_k, h * dr/du at u_k)
 };
 static_assert(sizeof(SolveRec) == 64, "SolveRec must stay one 64-byte line");
+
+
+// The tabulated residual r at p on one side (cubic Hermite between the two
+// knots around u); A is that side's leading shape, lnps = ln p_s and rA = 1/A.
+// A side without a table has all knots zero: r = 0.
+__host__ __device__ inline float table_residual(const SolveRec& R, bool lower, float A, float lnp, float lnps, float rA)
+{
+    const half2_t* K = R.knot[lower ? 0 : 1];
+    const float q = fmaxf((lnp - lnps) * f32_rcp(kLnPmin - lnps), 0.0f);
+    const float u = fminf(A < kVmapShape ? f32_exp((lnp - lnps) * rA)                          // (p/p_s)^(1/A)
+                                         : f32_exp(f32_ln(q) * (1.0f / 3.0f)),                // q^(1/3)
+                          1.0f);
+    const float g = u * (float)(kKnots - 1);
+    const int j = g < (float)(kKnots - 2) ? (int)g : kKnots - 2;
+    const float w = g - (float)j, w1 = 1.0f - w;
+    const half2_t k0 = K[j], k1 = K[j + 1];
+    return (1.0f + 2.0f * w) * w1 * w1 * (float)k0.x + w * w1 * w1 * (float)k0.y +
+           w * w * (3.0f - 2.0f * w) * (float)k1.x - w * w * w1 * (float)k1.y;
+}
+
+__host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaStats* st = nullptr,
+                                            const SolveRec* R = nullptr)
+{
+    const bool lower = z <= (double)E.us;
+    const double A = lower ? E.a : E.b;
+    const double B = lower ? E.b : E.a;
+    const double p = lower ? z : 1.0 - z;
+    const double lnB = E.lnB;
+
+    // ---- FP32 stage
+    const float Af = (float)A, Bf = (float)B;
+    const float lnpf = f32_ln((float)p);
+    const float rA = f32_rcp(Af);
+    const float ts = (Af + 1.0f) * f32_rcp(Af + Bf + 2.0f);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    // the leading term and the constants are formed in FP64: for tiny A the
+    // two logs cancel to O(A) and the FP32 difference would be noise
+    const double lnA = log(A), lnp = log(p);
+    const float c0f = (float)(-(lnB + lnA));
+    float y = (float)((lnp + lnA + lnB) / A);
+    if (R && y > -1e30f) y += table_residual(*R, lower, Af, lnpf, f32_ln(lower ? E.us : 1.0f - E.us), rA);
+    y = fmaxf(fminf(y, f32_ln(ts)), -1e30f);
+    // below these t the loss rounds to 0 (lower side, FP32 loss) or x to 1
+    // (upper side, FP64): no need to iterate further
+    const float yfloor = lower ? -110.0f : -40.0f;
+    int it32 = 0;
+    for (; it32 < 12 && y > yfloor; ++it32) {
+        const float t = f32_exp(y);
+        const float w = 1.0f - t;
+        const float l1t = f32_log1m(t, w);
+        float num, den;
+        beta_cf<float>(t, Af, Bf, 2e-7f, 48, num, den);
+        const float rnum = f32_rcp(num);
+        const float f = Af * y + Bf * l1t + c0f + f32_ln(den * rnum) - lnpf;   // ln(1/T) = ln(den/num)
+        float dy = -(f * w * den) * (rA * rnum);
+        // Halley's correction (f''/f' = A - (B-1) t/(1-t) - f', see newton32)
+        const float hc = 0.5f * ((Af - (Bf - 1.0f) * t * f32_rcp(w)) * dy + f);
+        if (fabsf(hc) < 0.5f) dy *= f32_rcp(1.0f + hc);
+        const float yn = fmaxf(fminf(y + dy, ymax), -1e30f);
+        const float step = yn - y;
+        y = yn;
+        if (fabsf(step) <= 2e-3f * fmaxf(1.0f, fabsf(y))) break;
+    }
+
+    // ---- FP64 polish
+    const double ts64 = (A + 1.0) / (A + B + 2.0);
+    const double ymax64 = log(fmin(1.1 * ts64, 0.5 * (1.0 + ts64)));
+    double yd = (double)y;
+    int it64 = 0;
+    for (; it64 < 6 && yd > (double)yfloor; ++it64) {
+        const double t = exp(yd);
+        const double l1t = log1p(-t);
+        double num, den;
+        beta_cf<double>(t, A, B, 1e-13, 200, num, den);
+        const double T = num / den;
+        const double f = A * yd + B * l1t - lnB - lnA - log(T) - lnp;
+        double dy = -f * (1.0 - t) / (A * T);
+        const double hc = 0.5 * ((A - (B - 1.0) * t / (1.0 - t)) * dy + f);
+        if (fabs(hc) < 0.5) dy /= 1.0 + hc;
+        const double yn = fmax(fmin(yd + dy, ymax64), -1e300);
+        const double step = yn - yd;
+        yd = yn;
+        // cubic convergence: after a step below 1e-4 the error is of order 1e-12
+        if (fabs(step) <= 1e-4) break;
+    }
+    if (st) {
+        st->it32 = it32;
+        st->it64 = it64;
+    }
+    return lower ? exp(yd) : -expm1(yd);
+}
+
+// Draws whose smaller shape parameter is below this take the FP64 polish; at
+// or above it the FP32 solve alone is accurate to a few 1e-6 relative (the
+// quantile's sensitivity to an error in ln I grows like 1/shape).
+constexpr double kPolishShape = 0.2;
+
+__host__ __device__ inline bool needs_polish(const EntryRec& E)
+{
+    return (E.a < E.b ? E.a : E.b) < kPolishShape;
+}
 
 // Knots of one side, out[2k] = r_k and out[2k+1] = h * dr/du at u_k.  A side
 // no draw reaches, or one whose knots leave FP64 range, is left zero (the
@@ -386,11 +416,7 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
     R.pol = needs_polish(E) ? 1u : 0u;
     for (int side = 0; side < 2; ++side) {
         float v[2 * kKnots];
-        if (R.pol) {
-            for (int k = 0; k < 2 * kKnots; ++k) v[k] = 0.0f;
-        } else {
-            knot_side(E, side == 0, v);
-        }
+        knot_side(E, side == 0, v);
         for (int k = 0; k < kKnots; ++k) {
             half2_t q;
             q.x = (_Float16)v[2 * k];
@@ -495,18 +521,7 @@ __device__ inline float inv_beta32(float z, const SolveRec& R)
     const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
     const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
     const float lnps = f32_ln(lower ? R.us : 1.0f - R.us);
-    // the tabulated residual at u, cubic Hermite between the two knots around it
-    const half2_t* K = R.knot[lower ? 0 : 1];
-    const float q = fmaxf((lnp - lnps) * f32_rcp(kLnPmin - lnps), 0.0f);
-    const float u = fminf(A < kVmapShape ? f32_exp((lnp - lnps) * rA)                    // (p/p_s)^(1/A)
-                                         : exp2f(__builtin_amdgcn_logf(q) * (1.0f / 3.0f)),   // q^(1/3)
-                          1.0f);
-    const float g = u * (float)(kKnots - 1);
-    const int j = min((int)g, kKnots - 2);
-    const float w = g - (float)j, w1 = 1.0f - w;
-    const half2_t k0 = K[j], k1 = K[j + 1];
-    const float r = (1.0f + 2.0f * w) * w1 * w1 * (float)k0.x + w * w1 * w1 * (float)k0.y +
-                    w * w * (3.0f - 2.0f * w) * (float)k1.x - w * w * w1 * (float)k1.y;
+    const float r = table_residual(R, lower, A, lnp, lnps, rA);
     return newton32<false>(fminf((lnp - c0) * rA + r, ymax), lower, A, B, lnp, c0, rA, ymax);
 }
 
@@ -538,7 +553,7 @@ __device__ inline float inv_beta32(float z, const EntryRec& E)
 // The inverse the plain layer kernel applies to one draw.
 __device__ inline double inv_beta_layer(double z, const EntryRec& E, const SolveRec& R)
 {
-    if (R.pol) return inv_beta(z, E);
+    if (R.pol) return inv_beta(z, E, nullptr, &R);
     return (double)inv_beta32((float)z, R);
 }
 
