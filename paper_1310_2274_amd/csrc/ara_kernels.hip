@@ -207,12 +207,12 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t
 // The layer kernels
 // ===========================================================================
 constexpr int kChunk = 64;                   // event slots per compaction round
-constexpr int kRound = 6;                    // draws per slot per drain round (LDS for 20 wavefronts per CU)
+constexpr int kRound = 6;                    // draws per slot per drain round (7.2 KB of LDS per wavefront)
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 
 // The FP64 polish of a deferred draw, out of line: a call whose registers
 // stay out of the layer kernel's allocation (inlined, they force spills in
-// the kernel's hot loops at five wavefronts per SIMD).
+// the kernel's hot loops).
 __device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E, const SolveRec* R)
 {
     if (E.a == 0.0) return (float)E.lnB;       // degenerate: the mean loss
@@ -237,13 +237,15 @@ __device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot
 // are still deferred keeps its partial loss in a small ring of pending chunks
 // and takes its occurrence terms once the last of them lands.  Every sum is a
 // fixed function of the trial, so the result does not depend on the launch.
+// Four wavefronts per SIMD (128 VGPRs): a fifth would leave 96, and the
+// spills that forces cost more than the occupancy gains.
 constexpr int kDefer = 128;                  // deferred-draw ring per wave (power of two)
 constexpr int kRing = 4;                     // chunks that may wait for deferred draws (four register sums)
 constexpr int kFinal = 0x7FFF;               // pending count of a finished (or empty) slot
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 4))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
