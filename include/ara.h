@@ -183,7 +183,8 @@ ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *lay
  * workgroup (defaults: 1 for the plain mode, 4 for the surrogate mode).
  * ara_set_trial_tile fixes it for a mode; ara_autotune times each
  * choice on the first n_trials trials for the given prepared layers (all of
- * one mode), keeps the fastest for that mode and returns it (ms_out,
+ * one mode), keeps the fastest for that mode (the current tile unless another
+ * is more than 3% faster) and returns it (ms_out,
  * optional: the time of each candidate 1, 2, 4, 8, float [4]).  Results do not
  * depend on the choice.  The mean mode has a fixed launch shape (catalog
  * slices of the per-event table in LDS, 16 wavefronts per workgroup) and

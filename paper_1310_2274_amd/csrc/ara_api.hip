@@ -1006,8 +1006,9 @@ ara_status ara_autotune(ara_ctx* c, int32_t yh, const int32_t* handles, int32_t 
     for (int32_t l = 0; l < n; ++l) outs[l] = (float*)((char*)c->ws_out.p + (size_t)l * align256((size_t)nt * 4));
     std::vector<uint32_t> seeds((size_t)n, 1u);
     const int32_t cand[4] = {1, 2, 4, 8};
-    int32_t best = c->wpb[mode];
-    float best_ms = 1e30f;
+    const int32_t cur = c->wpb[mode];
+    int32_t best = cur;
+    float best_ms = 1e30f, cur_ms = 1e30f;
     const bool prof = c->profiling;
     c->profiling = true;
     for (int ci = 0; ci < 4; ++ci) {
@@ -1023,12 +1024,16 @@ ara_status ara_autotune(ara_ctx* c, int32_t yh, const int32_t* handles, int32_t 
             HIPCHK(c, hipEventElapsedTime(&ms, c->k_start, c->k_stop));
         }
         if (ms_out) ms_out[ci] = ms;
+        if (cand[ci] == cur) cur_ms = ms;
         if (ms < best_ms) {
             best_ms = ms;
             best = cand[ci];
         }
     }
     c->profiling = prof;
+    // a slice's timing is noisier than the full run: keep the current tile
+    // unless another is clearly faster
+    if (cur_ms <= 1.03f * best_ms) best = cur;
     c->wpb[mode] = best;
     if (best_out) *best_out = best;
     return ARA_OK;
