@@ -131,6 +131,23 @@ def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_st
                     "trial far inside 1e-5 of the gross loss (tests/test_gpu_parity.py)"}
 
 
+def table_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s, plain_pml, plain_tvar):
+    """The table mode (per-entry tabulated inverse, no iteration) on the same
+    workload and draws as the plain path."""
+    t0 = time.perf_counter()
+    P.ara_run_layer(eng.ctx, yh, desc, P.MODE_TABLE, wl.seed, out)      # builds the XELTs' tables once
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    step_s, kms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_TABLE, wl.seed, out, rps, steps, warmup)
+    rel_p = np.abs(pml - plain_pml) / np.abs(plain_pml)
+    rel_t = np.abs(tvar - plain_tvar) / np.abs(plain_tvar)
+    return {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
+            "speedup_vs_plain": plain_step_s / step_s, "pml_rel_diff_vs_plain": rel_p.tolist(),
+            "tvar_rel_diff_vs_plain": rel_t.tolist(), "first_run_with_table_build_s": t_build,
+            "note": "per-draw error against the FP64 inverse below 2e-4 relative and 2e-5 of max_l "
+                    "(tests/test_gpu_table.py)"}
+
+
 def portfolio_leg(P, torch, synth, steps):
     wl = synth.portfolio()
     eng = P.Engine(0)
@@ -252,6 +269,7 @@ def main():
     ap.add_argument("--trials", type=int, default=800_000)
     ap.add_argument("--no-mean-leg", action="store_true", help="skip the streaming-phase (mean mode) leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--no-table", action="store_true", help="skip the table-mode leg")
     ap.add_argument("--sur-tuples", type=int, default=10_000_000)
     ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--sur-ckpt", default="")
@@ -329,6 +347,13 @@ def main():
                     "trial_events_per_s": N * K / mstep}
         log(f"mean mode: kernel {mk:.3f} ms = {gbs:.0f} GB/s")
 
+    tab = None
+    if not args.no_table:
+        tab = table_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar)
+        log(f"table mode: {tab['ms_per_step']:.2f} ms/step, x{tab['speedup_vs_plain']:.2f} vs plain, "
+            f"max PML/TVaR rel diff {max(tab['pml_rel_diff_vs_plain'] + tab['tvar_rel_diff_vs_plain']):.2e} "
+            f"(first run with the table build {tab['first_run_with_table_build_s']:.2f} s)")
+
     sur = None
     if not args.no_surrogate:
         sur = surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar,
@@ -360,6 +385,7 @@ def main():
         "roofline": roof,
         "roofline_streaming": mean_leg,
         "trial_tile": tune or None,
+        "table_mode": tab,
         "surrogate": sur,
         "portfolio": port,
         "correlated_portfolio": corr,

@@ -47,7 +47,8 @@ typedef int32_t ara_status;
 typedef enum {
     ARA_MODE_MEAN = 0,       /* primary uncertainty only: each loss is the XELT mean   */
     ARA_MODE_PLAIN = 1,      /* secondary uncertainty, exact inverse Beta (section 3)  */
-    ARA_MODE_SURROGATE = 2   /* secondary uncertainty, MLP sampler with exact fallback */
+    ARA_MODE_SURROGATE = 2,  /* secondary uncertainty, MLP sampler with exact fallback */
+    ARA_MODE_TABLE = 3       /* secondary uncertainty, per-entry tabulated inverse     */
 } ara_mode;
 
 /* Context on HIP device `device`.  hbm_budget_bytes caps the device memory the
@@ -306,6 +307,14 @@ ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, con
  * kernel applies it -- the FP32 solve alone where min(a, b) >= 0.2, FP32 plus
  * the FP64 polish below that.  Same arguments as ara_beta_quantile. */
 ara_status ara_beta_quantile_layer(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
+                                   double *x_out, void *hip_stream);
+/* ara_beta_quantile_table: the per-draw inverse of the table mode (section 3.3's
+ * inverse Beta read from a per-entry table, the paper's call for fast methods):
+ * seventeen FP32 Hermite knots per side of t_s around the leading-term
+ * asymptote, built in FP64, no iteration; relative error below 1e-4 and
+ * absolute error in x below 1e-5 on the paper's shapes.  u is taken in FP32
+ * (the draws are on the 2^-24 grid).  Same arguments as ara_beta_quantile. */
+ara_status ara_beta_quantile_table(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                                    double *x_out, void *hip_stream);
 
 #ifdef __cplusplus

@@ -22,7 +22,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libara.so")
 
 ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_NOMEM, ARA_E_BUDGET, ARA_E_DEVICE, ARA_E_STATE = 0, -1, -2, -3, -4, -5, -6
-MODE_MEAN, MODE_PLAIN, MODE_SURROGATE = 0, 1, 2
+MODE_MEAN, MODE_PLAIN, MODE_SURROGATE, MODE_TABLE = 0, 1, 2, 3
 STATUS_NAMES = {0: "ARA_OK", -1: "ARA_E_INVAL", -2: "ARA_E_RANGE", -3: "ARA_E_NOMEM", -4: "ARA_E_BUDGET",
                 -5: "ARA_E_DEVICE", -6: "ARA_E_STATE"}
 DEFAULT_RETURN_PERIODS = (10.0, 50.0, 100.0, 250.0)
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
             "ara_last_kernel_ms": (i32, [vp, C.POINTER(C.c_double)]),
             "ara_beta_quantile": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_beta_quantile_layer": (i32, [vp, vp, vp, vp, i64, vp, vp]),
+            "ara_beta_quantile_table": (i32, [vp, vp, vp, vp, i64, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -418,6 +419,11 @@ def ara_beta_quantile_layer(ctx, a, b, u, out=None, stream=None):
     return ara_beta_quantile(ctx, a, b, u, out, stream, _layer=True)
 
 
+def ara_beta_quantile_table(ctx, a, b, u, out=None, stream=None):
+    """The per-draw inverse of the table mode (per-entry tabulated inverse)."""
+    return ara_beta_quantile(ctx, a, b, u, out, stream, _layer="table")
+
+
 def ara_beta_quantile(ctx, a, b, u, out=None, stream=None, _layer=False):
     if isinstance(a, np.ndarray) or np.isscalar(a):
         a, b, u = np.broadcast_arrays(np.asarray(a, np.float64), np.asarray(b, np.float64), np.asarray(u, np.float64))
@@ -425,7 +431,8 @@ def ara_beta_quantile(ctx, a, b, u, out=None, stream=None, _layer=False):
     n = int(u.shape[0])
     if out is None:
         out = np.empty(n, dtype=np.float64)
-    fn = lib().ara_beta_quantile_layer if _layer else lib().ara_beta_quantile
+    fn = (lib().ara_beta_quantile_table if _layer == "table" else
+          lib().ara_beta_quantile_layer if _layer else lib().ara_beta_quantile)
     _check(ctx, fn(ctx, _ptr(a), _ptr(b), _ptr(u), n, _ptr(out), _stream(stream, a, b, u, out)))
     return out
 

@@ -17,6 +17,8 @@
 #include "ara_internal.hpp"
 #include "ara_surrogate.hpp"
 
+static_assert(ara::kModeTable == ARA_MODE_TABLE, "the layer kernel's table variant must match ARA_MODE_TABLE");
+
 using namespace ara;
 
 namespace {
@@ -40,7 +42,7 @@ struct EltRec {
     bool live = false;
     int32_t C = 0, n = 0;
     bool has_corr = false;
-    DevBuf idx, ent, cw, mean, sol;
+    DevBuf idx, ent, cw, mean, sol, tab;      // tab: built on the first table-mode run
     double ded = 0, lim = 0, share = 0;
 };
 
@@ -93,7 +95,7 @@ struct ara_ctx {
     int64_t sur_step = 0;
     DevBuf sur_P, sur_m, sur_v, sur_grad, sur_frag, sur_mask, sur_bias, sur_loss;
     DevBuf sur_tuples, sur_gpart, sur_lpart, sur_calib;
-    int32_t wpb[3] = {4, 1, 4};     // trial tile (wavefronts per workgroup) per mode
+    int32_t wpb[4] = {4, 1, 4, 1};  // trial tile (wavefronts per workgroup) per mode
     bool profiling = false;
     bool have_timing = false;
     hipEvent_t k_start = nullptr, k_stop = nullptr;
@@ -211,6 +213,21 @@ hipStream_t pick_stream(ara_ctx*, void* s) { return (hipStream_t)s; }
 
 bool is_finite(double x) { return std::isfinite(x); }
 
+// The table mode's per-entry records of each XELT of a layer, built (FP64, on
+// stream s) the first time a table-mode run uses the XELT and kept with it.
+ara_status ensure_tabs(ara_ctx* c, int mode, const std::vector<const EltRec*>& es, hipStream_t s)
+{
+    if (mode != ARA_MODE_TABLE) return ARA_OK;
+    for (const EltRec* ce : es) {
+        EltRec& e = const_cast<EltRec&>(*ce);      // the context owns the record
+        if (e.tab.p || e.n == 0) continue;
+        ara_status st = dev_alloc(c, e.tab, (size_t)e.n * sizeof(TabRec));
+        if (st) return st;
+        HIPCHK(c, launch_elt_tab(e.n, (const EntryRec*)e.ent.p, (TabRec*)e.tab.p, s));
+    }
+    return ARA_OK;
+}
+
 // Validate a layer and resolve its XELT handles.
 ara_status check_layer(ara_ctx* c, const YetRec& y, const ara_layer_desc* L, std::vector<const EltRec*>& out)
 {
@@ -261,6 +278,7 @@ void plan_layer(const ara_layer_desc* L, const std::vector<const EltRec*>& es, L
         d.cw = (const float2*)e.cw.p;
         d.mean = (const double*)e.mean.p;
         d.solve = (const SolveRec*)e.sol.p;
+        d.tab = (const TabRec*)e.tab.p;
         d.ded = e.ded;
         d.lim = e.lim;
         d.share = e.share;
@@ -287,6 +305,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
                align256(p.total * sizeof(EntryRec));
     if (p.has_corr) b += align256(p.total * 8);
     if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
+    if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
     return b;
 }
@@ -325,11 +344,17 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     }
     HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
     HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
-    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, s));
+    TabRec* ptab = nullptr;
+    if (mode == ARA_MODE_TABLE) {
+        ptab = (TabRec*)q;
+        q += align256(p.total * sizeof(TabRec));
+    }
+    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, ptab, s));
     p.dev.rows = rows;
     p.dev.pent = pent;
     p.dev.pcw = pcw;
     p.dev.psol = psol;
+    p.dev.ptab = ptab;
     if (mode == ARA_MODE_SURROGATE) {
         SurEntry* psur = (SurEntry*)q;
         q += align256(p.total * sizeof(SurEntry));
@@ -389,7 +414,7 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
         HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const uint32_t*)yr.soff.p,
                               (const uint32_t*)yr.scnt.p, c->ws_mean.p, yelt, s));
     else
-        HIPCHK(c, launch_layers(1, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
+        HIPCHK(c, launch_layers(mode, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
     if (c->profiling) {
         HIPCHK(c, hipEventRecord(c->k_stop, s));
         c->have_timing = true;
@@ -402,7 +427,7 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
                     float* const* yelt_outs, void* hip_stream, bool allow_host_out)
 {
     if (!c) return ARA_E_STATE;
-    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
+    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE && mode != ARA_MODE_TABLE)
         return fail(c, ARA_E_INVAL, "unknown mode %d", (int)mode);
     if (mode == ARA_MODE_SURROGATE && !c->sur_ready)
         return fail(c, ARA_E_STATE, "surrogate mode needs a trained or imported surrogate");
@@ -423,6 +448,7 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     int32_t maxJ = 0;
     for (int32_t l = 0; l < n_layers; ++l) {
         if ((st = check_layer(c, y, &layers[l], es))) return st;
+        if ((st = ensure_tabs(c, mode, es, s))) return st;
         plan_layer(&layers[l], es, plans[l]);
         tab_total += table_bytes(mode, y.C, plans[l]);
         has_corr |= plans[l].has_corr;
@@ -840,6 +866,7 @@ ara_status ara_free_elts(ara_ctx* c, const int32_t* h, int32_t n)
         dev_free(c, e.idx);
         dev_free(c, e.ent);
         dev_free(c, e.sol);
+        dev_free(c, e.tab);
         dev_free(c, e.cw);
         dev_free(c, e.mean);
         e.live = false;
@@ -890,7 +917,7 @@ ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode m
 {
     if (!c) return ARA_E_STATE;
     if (!handle || !layer) return fail(c, ARA_E_INVAL, "bad arguments to ara_prepare_layer");
-    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE)
+    if (mode != ARA_MODE_MEAN && mode != ARA_MODE_PLAIN && mode != ARA_MODE_SURROGATE && mode != ARA_MODE_TABLE)
         return fail(c, ARA_E_INVAL, "unknown mode %d", (int)mode);
     if (layer->n_elts < 1 || !layer->elt_handles) return fail(c, ARA_E_INVAL, "empty layer");
     const int32_t h0 = layer->elt_handles[0];
@@ -901,6 +928,7 @@ ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode m
     ara_status st = check_layer(c, pseudo, layer, es);
     if (st) return st;
     if ((st = begin_call(c, nullptr))) return st;
+    if ((st = ensure_tabs(c, mode, es, nullptr))) return st;
     PreparedRec pr;
     LayerPlan plan;
     plan_layer(layer, es, plan);
@@ -982,7 +1010,7 @@ ara_status ara_run_prepared(ara_ctx* c, int32_t yh, const int32_t* handles, int3
 ara_status ara_set_trial_tile(ara_ctx* c, ara_mode mode, int32_t wpb)
 {
     if (!c) return ARA_E_STATE;
-    if (mode < ARA_MODE_MEAN || mode > ARA_MODE_SURROGATE) return fail(c, ARA_E_INVAL, "unknown mode");
+    if (mode < ARA_MODE_MEAN || mode > ARA_MODE_TABLE) return fail(c, ARA_E_INVAL, "unknown mode");
     const bool ok = wpb == 1 || wpb == 2 || wpb == 4 || (wpb == 8 && mode != ARA_MODE_SURROGATE);
     if (!ok) return fail(c, ARA_E_INVAL, "trial tile %d not available for mode %d", wpb, (int)mode);
     c->wpb[mode] = wpb;
@@ -1174,7 +1202,7 @@ ara_status ara_normal_quantile(ara_ctx* c, const double* p, int64_t n, double* x
 }
 
 static ara_status beta_quantile_impl(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
-                                     double* x, void* hip_stream, bool layer)
+                                     double* x, void* hip_stream, int kind)   // 0 general, 1 layer, 2 table
 {
     if (!c) return ARA_E_STATE;
     if (n < 0 || (n > 0 && (!a || !b || !u || !x))) return fail(c, ARA_E_INVAL, "bad arguments to ara_beta_quantile");
@@ -1205,7 +1233,8 @@ static ara_status beta_quantile_impl(ara_ctx* c, const double* a, const double* 
             q += nb;
         }
     double* xo = dx ? x : (double*)q;
-    if (layer) HIPCHK(c, launch_beta_quantile_layer(ptr[0], ptr[1], ptr[2], n, xo, s));
+    if (kind == 1) HIPCHK(c, launch_beta_quantile_layer(ptr[0], ptr[1], ptr[2], n, xo, s));
+    else if (kind == 2) HIPCHK(c, launch_beta_quantile_table(ptr[0], ptr[1], ptr[2], n, xo, s));
     else HIPCHK(c, launch_beta_quantile(ptr[0], ptr[1], ptr[2], n, xo, s));
     if (!dx) HIPCHK(c, hipMemcpyAsync(x, xo, (size_t)n * 8, hipMemcpyDeviceToHost, s));
     if ((st = end_call(c, s))) return st;
@@ -1430,13 +1459,19 @@ ara_status ara_surrogate_eval(ara_ctx* c, const double* a, const double* b, cons
 ara_status ara_beta_quantile(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n, double* x,
                              void* hip_stream)
 {
-    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, false);
+    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, 0);
 }
 
 ara_status ara_beta_quantile_layer(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
                                    double* x, void* hip_stream)
 {
-    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, true);
+    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, 1);
+}
+
+ara_status ara_beta_quantile_table(ara_ctx* c, const double* a, const double* b, const double* u, int64_t n,
+                                   double* x, void* hip_stream)
+{
+    return beta_quantile_impl(c, a, b, u, n, x, hip_stream, 2);
 }
 
 }  // extern "C"

@@ -7,6 +7,7 @@
 namespace ara {
 
 constexpr int kMaxEltsPerLayer = 64;
+constexpr int kModeTable = 3;              // ARA_MODE_TABLE: the layer kernel's tabulated-inverse variant
 constexpr int kMaxRp = 16;
 constexpr float kSigmaClamp = 0.999f;      // sigma_beta <= 0.999 * sigma_beta_max
 
@@ -20,6 +21,7 @@ struct EltDev {
     const float2* cw;       // [n] (c_I, c_C) weights of section 3.2, or null if sigma_C == 0
     const double* mean;     // [n] mean loss mu_l
     const SolveRec* solve;  // [n] FP32 solve records with their start tables
+    const TabRec* tab;      // [n] tabulated-inverse records (built on the first table-mode run), or null
     double ded, lim, share; // financial terms I of the XELT
     int32_t n;
     int32_t pad;
@@ -38,6 +40,7 @@ struct LayerDev {
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
     const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
+    const TabRec* ptab;     // [sum n_j] tabulated-inverse records, packed like pent (table mode), or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
     float* ylt;             // [trial_end - trial_begin]
@@ -70,7 +73,10 @@ hipError_t launch_layer_count(int32_t C, int32_t J, const EltDev* elts, uint4* r
 size_t scan_scratch_words(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, hipStream_t s);
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, SolveRec* psol, hipStream_t s);
+                             EntryRec* pent, float2* pcw, SolveRec* psol, TabRec* ptab, hipStream_t s);
+hipError_t launch_elt_tab(int32_t n, const EntryRec* ent, TabRec* tab, hipStream_t s);
+hipError_t launch_beta_quantile_table(const double* a, const double* b, const double* u, int64_t n, double* x,
+                                      hipStream_t s);
 hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,
                              float* occ_tab, hipStream_t s);
 // wpb: wavefronts (= trials) per workgroup, 1, 2, 4 or 8 -- the trial tile

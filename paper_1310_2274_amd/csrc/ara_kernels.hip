@@ -72,6 +72,14 @@ __global__ void k_elt_solve(int32_t n, const EntryRec* __restrict__ ent, SolveRe
     sol[r] = make_solve_rec(ent[r]);
 }
 
+// Tabulated-inverse records, one thread per entry, FP64.
+__global__ void k_elt_tab(int32_t n, const EntryRec* __restrict__ ent, TabRec* __restrict__ tab)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    tab[r] = make_tab_rec(ent[r]);
+}
+
 __global__ void k_validate_ids(const int32_t* __restrict__ ev, int64_t n, int32_t C, unsigned int* bad)
 {
     unsigned int local = 0;
@@ -100,7 +108,7 @@ __global__ void k_layer_count(int32_t C, int32_t J, const EltDev* __restrict__ e
 
 __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ elts, const uint32_t* __restrict__ off,
                              uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw,
-                             SolveRec* __restrict__ psol)
+                             SolveRec* __restrict__ psol, TabRec* __restrict__ ptab)
 {
     const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= C) return;
@@ -118,6 +126,7 @@ __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ el
         pent[o] = E;
         if (pcw) pcw[o] = X.cw ? X.cw[i] : make_float2(1.0f, 0.0f);
         if (psol) psol[o] = X.solve[i];
+        if (ptab) ptab[o] = X.tab[i];
         if (rank < kRowPolBits && needs_polish(E)) pol |= 1u << rank;
         ++o;
     }
@@ -244,7 +253,7 @@ constexpr int kRing = 4;                     // chunks that may wait for deferre
 constexpr int kFinal = 0x7FFF;               // pending count of a finished (or empty) slot
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
-template <bool HAS_CORR, int WPB>
+template <bool HAS_CORR, int WPB, bool TAB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 4))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
@@ -383,7 +392,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     const int j = __ffsll((unsigned long long)mask) - 1;
                     mask &= mask - 1;
                     const int rk = rank + i;
-                    const uint32_t pol = rk < kRowPolBits ? (rw >> (7 + rk)) & 1u : L.psol[off + (uint32_t)rk].pol;
+                    // the table mode takes every draw from its table: nothing is deferred
+                    const uint32_t pol = TAB ? 0u : rk < kRowPolBits ? (rw >> (7 + rk)) & 1u : L.psol[off + (uint32_t)rk].pol;
                     QI[pos + i] = off + (uint32_t)rk;
                     QM[pos + i] = (uint16_t)(lane | (pol << 7) | (j << 8));
                 }
@@ -429,9 +439,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         const int q = L32[idx];
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
-                        const SolveRec& R = L.psol[pi];
                         const float z = HAS_CORR ? QV[q] : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
-                        const float loss = R.maxl * inv_beta32(z, R);
+                        float loss;
+                        if (TAB) {
+                            const TabRec& T = L.ptab[pi];
+                            loss = T.maxl * tab_inverse(z, T);
+                        } else {
+                            const SolveRec& R = L.psol[pi];
+                            loss = R.maxl * inv_beta32(z, R);
+                        }
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
                     }
@@ -828,6 +844,29 @@ __global__ void k_beta_quantile_layer(const double* __restrict__ a, const double
 // ===========================================================================
 // Launchers
 // ===========================================================================
+__global__ void k_beta_quantile_table(const double* __restrict__ a, const double* __restrict__ b,
+                                      const double* __restrict__ u, int64_t n, double* __restrict__ x)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    EntryRec E;
+    E.a = a[i];
+    E.b = b[i];
+    E.lnB = log_beta(E.a, E.b);
+    E.us = (float)beta_inc_lower((E.a + 1.0) / (E.a + E.b + 2.0), E.a, E.b, E.lnB);
+    E.maxl = 1.0f;
+    const TabRec T = make_tab_rec(E);               // as the table mode holds it
+    x[i] = (double)tab_inverse((float)u[i], T);
+}
+
+hipError_t launch_beta_quantile_table(const double* a, const double* b, const double* u, int64_t n, double* x,
+                                      hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_beta_quantile_table, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, a, b, u, n, x);
+    return hipGetLastError();
+}
+
 hipError_t launch_beta_quantile_layer(const double* a, const double* b, const double* u, int64_t n, double* x,
                                       hipStream_t s)
 {
@@ -879,6 +918,12 @@ hipError_t launch_elt_prepare(int32_t n, const double* mean, const double* sig_i
     return hipGetLastError();
 }
 
+hipError_t launch_elt_tab(int32_t n, const EntryRec* ent, TabRec* tab, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_elt_tab, dim3(nblocks(n, 64)), dim3(64), 0, s, n, ent, tab);
+    return hipGetLastError();
+}
+
 hipError_t launch_elt_solve(int32_t n, const EntryRec* ent, SolveRec* sol, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_elt_solve, dim3(nblocks(n, 64)), dim3(64), 0, s, n, ent, sol);
@@ -913,9 +958,9 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
 }
 
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, SolveRec* psol, hipStream_t s)
+                             EntryRec* pent, float2* pcw, SolveRec* psol, TabRec* ptab, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol);
+    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol, ptab);
     return hipGetLastError();
 }
 
@@ -932,10 +977,15 @@ static void launch_layers_wpb(int mode, bool has_corr, const YetDev& y, int64_t 
 {
     const int64_t n = t1 - t0;
     const dim3 grid(nblocks(n, WPB)), block(64 * WPB);
-    if (has_corr)
-        hipLaunchKernelGGL((k_layer_plain<true, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+    const bool tab = mode == kModeTable;
+    if (has_corr && tab)
+        hipLaunchKernelGGL((k_layer_plain<true, WPB, true>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+    else if (has_corr)
+        hipLaunchKernelGGL((k_layer_plain<true, WPB, false>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+    else if (tab)
+        hipLaunchKernelGGL((k_layer_plain<false, WPB, true>), grid, block, 0, s, y, t0, t1, layers, n_layers);
     else
-        hipLaunchKernelGGL((k_layer_plain<false, WPB>), grid, block, 0, s, y, t0, t1, layers, n_layers);
+        hipLaunchKernelGGL((k_layer_plain<false, WPB, false>), grid, block, 0, s, y, t0, t1, layers, n_layers);
 }
 
 int32_t mean_slices(int32_t C)
@@ -1003,7 +1053,6 @@ hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, i
                          int32_t n_layers, int32_t wpb, hipStream_t s)
 {
     if (t1 - t0 <= 0 || n_layers <= 0) return hipSuccess;
-    (void)mode;
     switch (wpb) {
         case 1: launch_layers_wpb<1>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
         case 2: launch_layers_wpb<2>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
