@@ -230,10 +230,30 @@ __device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E, con
 
 // The correlated draw's z (two uniforms, two FP64 normal quantiles, one
 // normal CDF), out of line for the same reason.
-__device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed,
-                                                   uint32_t prog, const float2* pcw, uint32_t pi)
+// The event's correlated uniform u_C (one per trial and slot, the same for
+// every program and XELT) and its normal quantile, formed once per event.
+struct CorrEvent {
+    double qc;      // Phi^-1(u_C)
+    float uc;       // u_C
+};
+__device__ __attribute__((noinline)) CorrEvent corr_event(uint32_t trial, uint32_t slot, uint32_t seed)
 {
-    return draw_z<true>(trial, slot, j, seed, prog, pcw, pi);
+    CorrEvent c;
+    c.uc = u01(philox_word0(trial, slot, 0xFFFFFFFFu, 1u, seed, 0xFFFFFFFFu));
+    c.qc = normal_quantile((double)c.uc);
+    return c;
+}
+
+// One draw's z from its own uniform and the event's shared part: the same
+// value draw_z<true> forms, with u_C and its quantile taken from corr_event.
+__device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot, uint32_t j, uint32_t seed,
+                                                   uint32_t prog, const float2* pcw, uint32_t pi, float uc, double qc)
+{
+    const double ui = (double)u01(philox_word0(trial, slot, j, 0u, seed, prog));
+    const float2 w = pcw[pi];
+    if (w.y == 0.0f) return ui;
+    if (w.x == 0.0f) return (double)uc;
+    return normcdf((double)w.x * normal_quantile(ui) + (double)w.y * qc);
 }
 
 // Plain path, one wave per trial.  Each chunk of 64 event slots is drained in
@@ -264,6 +284,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
     __shared__ uint32_t didx[WPB][kDefer];
     __shared__ uint32_t dmeta[WPB][kDefer];
     __shared__ double dz[HAS_CORR ? WPB : 1][HAS_CORR ? kDefer : 1];
+    __shared__ double qcs[HAS_CORR ? WPB : 1][HAS_CORR ? 64 : 1];     // correlated layers: per slot Phi^-1(u_C)
+    __shared__ float ucs[HAS_CORR ? WPB : 1][HAS_CORR ? 64 : 1];      //   and u_C
     __shared__ float pcs[WPB][kRing][64];
     __shared__ short pns[WPB][kRing][64];
     __shared__ int rchunk[WPB][kRing];
@@ -278,6 +300,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
     uint32_t* DI = didx[w];          // deferred draws: packed entry index
     uint32_t* DM = dmeta[w];         //   slot within the trial | XELT position << 24
     double* DZ = dz[HAS_CORR ? w : 0];  //   z (correlated layers: formed in the classify pass)
+    double* QC = qcs[HAS_CORR ? w : 0]; // correlated layers, per slot of the chunk: Phi^-1(u_C)
+    float* UC = ucs[HAS_CORR ? w : 0];  //   and u_C
     float (*PC)[64] = pcs[w];        // pending chunks: partial event loss per slot
     short (*PN)[64] = pns[w];        //   deferred draws outstanding per slot
     int* RC = rchunk[w];             //   chunk held by each ring slot (-1: free)
@@ -375,6 +399,13 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             const bool valid = k < len;
             uint4 rr = make_uint4(0, 0, 0, 0);
             if (valid) rr = L.rows[y.ev[row + k]];
+            if (HAS_CORR) {
+                // the event's correlated uniform and its quantile, once per slot
+                CorrEvent ce{0.0, 0.0f};
+                if (valid && (rr.x | rr.y) != 0u) ce = corr_event(tr, (uint32_t)k, L.seed);
+                QC[lane] = ce.qc;
+                UC[lane] = ce.uc;
+            }
             uint64_t mask = (uint64_t)rr.x | ((uint64_t)rr.y << 32);
             const uint32_t off = rr.z;
             const uint32_t rw = rr.w;
@@ -412,7 +443,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     double zc = 0.0;
                     if (HAS_CORR && in) {
                         const uint32_t pi = QI[q], meta = QM[q];
-                        zc = corr_z(tr, (uint32_t)base + (meta & 63u), meta >> 8, L.seed, L.prog, L.pcw, pi);
+                        const uint32_t own = meta & 63u;
+                        zc = corr_z(tr, (uint32_t)base + own, meta >> 8, L.seed, L.prog, L.pcw, pi, UC[own], QC[own]);
                     }
                     if (in) {
                         if (pol) {
