@@ -41,7 +41,7 @@ VALU_OPS_PER_DRAW = 753.6
 # Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2.0 * 25761941.1 + 1.0 * 396516.3) * 1024
+TRAFFIC_BYTES = 8 * (2.0 * 25762273.3 + 1.0 * 396516.7) * 1024
 
 
 def log(msg):

@@ -132,3 +132,26 @@ def test_table_mode_tiles_prepared_and_deterministic(eng):
     for h in hs:
         P.ara_free_layer(eng.ctx, h)
     P.ara_set_trial_tile(eng.ctx, P.MODE_TABLE, 1)
+
+
+def test_table_mode_yelt_and_occurrence_outputs(eng):
+    # the per-occurrence outputs of the table mode: each occurrence's loss net of
+    # XELT and occurrence terms, and the largest per trial
+    torch = torch_cuda()
+    wl = synth.custom(130, 63, 400, 3, 50, 150, seed=19)
+    lay = wl.layers[0]
+    yh = eng.load_yet(wl.yet(), wl.catalog_size)
+    desc = eng.load_layer(lay, wl.catalog_size)
+    t0, t1 = 17, 101
+    y = torch.empty(t1 - t0, device="cuda")
+    om = torch.empty(t1 - t0, device="cuda")
+    ye = torch.full(((t1 - t0) * 63,), -7.0, device="cuda")
+    P.ara_run_layer_yelt(eng.ctx, yh, desc, P.MODE_TABLE, 23, t0, t1, y, ye, om)
+    torch.cuda.synchronize()
+    trials = np.arange(t0, t1)
+    yo, g, omo, yeo = oracle.run_layer(lay, wl.yet()[trials], trials, wl.catalog_size, 23, yelt=True)
+    _assert_table_close(y.cpu().numpy(), yo, g, "table YLT")
+    _assert_table_close(om.cpu().numpy(), omo, g, "table max occurrence")
+    ye = ye.cpu().numpy().astype(np.float64).reshape(t1 - t0, 63)
+    assert np.all(np.abs(ye - yeo) <= (TAB_REL * g + ABS_TOL)[:, None])
+    assert np.array_equal(ye.max(axis=1), om.cpu().numpy().astype(np.float64))
