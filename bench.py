@@ -37,11 +37,11 @@ PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
 PEAK_VALU_TOPS = 157.3 / 2
 # VALU lane-instructions per draw of the plain layer kernel on this workload,
 # SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 753.6
+VALU_OPS_PER_DRAW = 746.2
 # Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2.0 * 25762273.3 + 1.0 * 396516.7) * 1024
+TRAFFIC_BYTES = 8 * (2.0 * 25379206.7 + 1.0 * 344259.3) * 1024
 
 
 def log(msg):

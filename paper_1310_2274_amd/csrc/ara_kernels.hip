@@ -375,8 +375,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             PN[2][lane] -= n2;
             PC[3][lane] += a3;
             PN[3][lane] -= n3;
-            dh = (dh + m) & (kDefer - 1);
-            dn -= m;
+            dh = __builtin_amdgcn_readfirstlane((dh + m) & (kDefer - 1));
+            dn = __builtin_amdgcn_readfirstlane(dn - m);
             wave_sync();
             for (int r = 0; r < kRing; ++r)
                 if (r != open_ring) settle(r);
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             while (true) {
                 const int take = remaining < kRound ? remaining : kRound;
                 const int incl = wave_incl_scan(take);
-                const int total = __shfl(incl, 63, 64);
+                const int total = __builtin_amdgcn_readlane(incl, 63);     // wave-uniform (scalar)
                 if (total == 0) break;
                 const int pos = incl - take;
                 for (int i = 0; i < take; ++i) {
@@ -459,8 +459,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                             if (HAS_CORR) QV[q] = (float)zc;          // the FP32 solve takes z in FP32
                         }
                     }
-                    n32 += __popcll(b32);
-                    dn += __popcll(b64);
+                    n32 = __builtin_amdgcn_readfirstlane(n32 + __popcll(b32));
+                    dn = __builtin_amdgcn_readfirstlane(dn + __popcll(b64));
                     wave_sync();
                     if (dn >= 64) flush(64, r);
                 }

@@ -453,7 +453,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
             while (true) {
                 const int take = remaining < kSurRound ? remaining : kSurRound;
                 const int incl = wave_incl_scan(take);
-                const int total = __shfl(incl, 63, 64);
+                const int total = __builtin_amdgcn_readlane(incl, 63);     // wave-uniform (scalar)
                 if (total == 0) break;
                 const int pos = incl - take;
                 for (int i = 0; i < take; ++i) {
