@@ -317,7 +317,9 @@ def main():
 
     tune = {}
     if not args.no_autotune:
-        tune["plain"] = autotune(P, eng, yh, desc, P.MODE_PLAIN, min(N, 100_000))
+        # on the whole YET (two passes per candidate, about 1.5 s): on a 100,000-trial slice two
+        # wavefronts per workgroup come out ~3% faster, on the full 800,000-trial grid ~2% slower
+        tune["plain"] = autotune(P, eng, yh, desc, P.MODE_PLAIN, N)
         log(f"trial tile (plain): {tune['plain']['waves_per_workgroup']} waves/workgroup, "
             f"slice ms {tune['plain']['slice_ms']}")
     step_s, kernel_ms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps,

@@ -530,6 +530,7 @@ constexpr int kMeanWaves = 16;               // wavefronts per workgroup
 constexpr int kMeanTile = 1024;              // trials per workgroup
 constexpr int kLanesPerTrial = 16;           // lanes streaming one trial's group
 constexpr int kTrialsPerWave = 64 / kLanesPerTrial;
+constexpr int kMeanPre = 4;                 // int4 loads per lane kept in flight one batch ahead
 
 // The slice-major copy: group (slice s, trial t) holds trial t's ids that
 // fall in slice s, in time order, padded with -1 to a multiple of four; the
@@ -583,7 +584,8 @@ __global__ __launch_bounds__(256) void k_yet_scatter(YetDev y, int32_t slice_len
 
 // kLanesPerTrial lanes per trial, kTrialsPerWave trials per wavefront at a
 // time, so each wavefront keeps several 16-byte loads of several trials in
-// flight; the next trials' group offsets are fetched one iteration ahead.
+// flight; the next batch's ids and the offsets of the batch after it are
+// fetched while a batch is summed.
 __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_t t0, int64_t t1,
                                                                  const LayerDev* __restrict__ layers, int32_t l,
                                                                  const int32_t* __restrict__ ev2,
@@ -621,22 +623,38 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
             n4 = (int32_t)(gcnt[g] >> 2);
         }
     };
-    int64_t at_next;
-    int32_t n4_next;
-    locate(tb + kTrialsPerWave * w + grp, at_next, n4_next);
-    for (int64_t i0 = tb + kTrialsPerWave * w; i0 < te; i0 += kTrialsPerWave * kMeanWaves) {
+    // The first kMeanPre 16-byte loads of each lane's share of a group are
+    // issued one batch of trials ahead, so the next trials' ids stream in
+    // while this batch is summed; a group longer than kMeanPre * 16 int4
+    // (rare: 256 ids of one slice in one trial) reads the rest in place.
+    auto fetch = [&](int64_t at_, int32_t n4_, v4i* dst) {
+        const v4i* __restrict__ p = reinterpret_cast<const v4i*>(ev2 + at_);
+#pragma unroll
+        for (int r = 0; r < kMeanPre; ++r) {
+            const int32_t q = sub + r * kLanesPerTrial;
+            dst[r] = q < n4_ ? __builtin_nontemporal_load(p + q) : v4i{-1, -1, -1, -1};
+        }
+    };
+    constexpr int64_t kStride = kTrialsPerWave * kMeanWaves;
+    const int64_t first = tb + kTrialsPerWave * w + grp;
+    int64_t at, at1;
+    int32_t n4, n41;
+    locate(first, at, n4);
+    v4i e[kMeanPre];
+    fetch(at, n4, e);
+    locate(first + kStride, at1, n41);                   // offsets of the next batch
+    for (int64_t i0 = tb + kTrialsPerWave * w; i0 < te; i0 += kStride) {
         const int64_t i = i0 + grp;
         const bool live = i < te;
-        const int64_t at = at_next;
-        const int32_t n4 = n4_next;
-        locate(i + kTrialsPerWave * kMeanWaves, at_next, n4_next);   // the next group's offsets, in flight early
-        const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(ev2 + at);
+        v4i en[kMeanPre];
+        fetch(at1, n41, en);                             // the next batch's ids, in flight during this one
+        int64_t at2;
+        int32_t n42;
+        locate(i + 2 * kStride, at2, n42);               // and the offsets of the batch after it
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, m = 0.0f;
-#pragma unroll 8
-        for (int32_t q = sub; q < n4; q += kLanesPerTrial) {
-            const v4i e = __builtin_nontemporal_load(v4 + q);
-            const uint32_t u0 = (uint32_t)(e.x - lo), u1 = (uint32_t)(e.y - lo);
-            const uint32_t u2 = (uint32_t)(e.z - lo), u3 = (uint32_t)(e.w - lo);
+        auto add4 = [&](const v4i& x) {
+            const uint32_t u0 = (uint32_t)(x.x - lo), u1 = (uint32_t)(x.y - lo);
+            const uint32_t u2 = (uint32_t)(x.z - lo), u3 = (uint32_t)(x.w - lo);
             const float v0 = u0 < un ? stab[u0] : 0.0f;          // -1 padding falls outside
             const float v1 = u1 < un ? stab[u1] : 0.0f;
             const float v2 = u2 < un ? stab[u2] : 0.0f;
@@ -646,7 +664,19 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
             a2 += v2;
             a3 += v3;
             m = fmaxf(m, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
-        }
+        };
+#pragma unroll
+        for (int r = 0; r < kMeanPre; ++r) add4(e[r]);
+        const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(ev2 + at);
+#pragma unroll 1
+        for (int32_t q = sub + kMeanPre * kLanesPerTrial; q < n4; q += kLanesPerTrial)
+            add4(__builtin_nontemporal_load(v4 + q));
+#pragma unroll
+        for (int r = 0; r < kMeanPre; ++r) e[r] = en[r];
+        at = at1;
+        n4 = n41;
+        at1 = at2;
+        n41 = n42;
         float S = a0, Sc = 0.0f;
         neumaier_add(S, Sc, a1);
         neumaier_add(S, Sc, a2);
