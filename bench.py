@@ -42,6 +42,9 @@ VALU_OPS_PER_DRAW = 746.2
 # the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
 # measured on the 100,000-trial slice and scaled by 8.
 TRAFFIC_BYTES = 8 * (2.0 * 25379206.7 + 1.0 * 344259.3) * 1024
+# The same for one 800,000-trial mean-mode pass (k_mean_slice + k_mean_finish,
+# profiles/k_mean_slice_paper800k_trace.md).
+MEAN_TRAFFIC_BYTES = (2.0 * (1669229.0 + 28132.0) + 1.0 * (56297.0 + 3125.0)) * 1024
 
 
 def log(msg):
@@ -346,7 +349,8 @@ def main():
         mean_leg = {"bound": "hbm", "kernel": "k_mean_slice + k_mean_finish", "kernel_ms": mk, "achieved": gbs,
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
                     "algorithmic_bytes": N * K * 4 + N * 4, "ms_per_step": mstep * 1e3,
-                    "trial_events_per_s": N * K / mstep}
+                    "trial_events_per_s": N * K / mstep,
+                    "traffic": MEAN_TRAFFIC_BYTES if N == 800_000 else None}
         log(f"mean mode: kernel {mk:.3f} ms = {gbs:.0f} GB/s")
 
     tab = None
