@@ -201,6 +201,27 @@ def run_layer(layer, yet_rows: np.ndarray, trial_ids: Sequence[int], catalog_siz
     return (ylt, gross, omax, ye) if yelt else (ylt, gross, omax)
 
 
+# ---------------------------------------------------------------- section 2.3
+def yelt_increments(yelt: np.ndarray, agg_retention: float, agg_limit: float, lengths=None) -> np.ndarray:
+    """Per-occurrence aggregate increments, from the definition: for each trial
+    (row), S_k = sum of its occurrence losses o_0..o_k, A_k =
+    min(max(S_k - AggR, 0), AggL) and the increment of occurrence k is
+    A_k - A_{k-1} with A_{-1} = 0 (the aggregate terms act on the running sum,
+    section 2.3).  ``lengths`` (optional) limits row i to its first lengths[i]
+    occurrences; the rest of the row is left 0."""
+    yelt = np.asarray(yelt, dtype=np.float64)
+    out = np.zeros_like(yelt)
+    for i in range(yelt.shape[0]):
+        n = yelt.shape[1] if lengths is None else int(lengths[i])
+        a_prev, s = 0.0, 0.0
+        for k in range(n):
+            s += yelt[i, k]
+            a = min(max(s - agg_retention, 0.0), agg_limit)
+            out[i, k] = a - a_prev
+            a_prev = a
+    return out
+
+
 # ---------------------------------------------------------------- section 2.4
 def risk_measures(ylt: np.ndarray, return_periods: Sequence[float]):
     """PML and TVaR at each return period RP, from the definition:

@@ -59,23 +59,64 @@ def forward(P, T):
     return xh, loss, (X, Z1, H1, Z2, H2, xh, x)
 
 
-def grad(P, T):
-    """Gradient of the mean squared error with respect to the flat parameters."""
+def _round(v, mode, rng):
+    """The value a half-precision operand takes: unchanged (mode None), rounded
+    to the nearest FP16 value ('fp16'), or moved by a random relative amount of
+    up to 2^-10, one FP16 unit in the last place ('perturb')."""
+    if mode is None:
+        return v
+    if mode == "fp16":
+        return v.astype(np.float16).astype(np.float64)
+    return v * (1.0 + 2.0 ** -10 * rng.uniform(-1.0, 1.0, v.shape))
+
+
+def grad(P, T, half=None, rng=None):
+    """Gradient of the mean squared error with respect to the flat parameters.
+
+    ``half`` applies ``_round`` where a half-precision kernel would hold an
+    operand in FP16: the hidden activations g(Z1) and g(Z2), and dL/dZ2 as
+    an operand of dW2 and dL/dH1 (db2 sums it unrounded).  dL/dZ2 is rounded
+    scaled by n * 1024, as a kernel keeps it (the per-row derivative times a
+    loss scale of 1024), so small values stay clear of FP16's subnormals."""
     W1, b1, W2, b2, w3, b3 = unpack(P)
-    xh, loss, (X, Z1, H1, Z2, H2, xh, x) = forward(P, T)
+    T = np.asarray(T, dtype=np.float64)
+    X, base, x = T[:, 0:3], T[:, 3], T[:, 4]
     n = X.shape[0]
+    Z1 = X @ W1.T + b1
+    H1 = _round(g(Z1), half, rng)
+    Z2 = H1 @ W2.T + b2
+    H2 = _round(g(Z2), half, rng)
+    o = H2 @ w3 + b3
+    xh = sigmoid(base + o)
+    loss = np.mean((xh - x) ** 2)
     do = 2.0 * (xh - x) * xh * (1.0 - xh) / n          # dL/do per row
     dw3 = H2.T @ do
     db3 = do.sum()
     dH2 = np.outer(do, w3)
     dZ2 = dH2 * g_prime(Z2)
-    dW2 = dZ2.T @ H1
+    sc = n * 1024.0
+    dZ2h = _round(dZ2 * sc, half, rng) / sc
+    dW2 = dZ2h.T @ H1
     db2 = dZ2.sum(0)
-    dH1 = dZ2 @ W2
+    dH1 = dZ2h @ W2
     dZ1 = dH1 * g_prime(Z1)
     dW1 = dZ1.T @ X
     db1 = dZ1.sum(0)
     return np.concatenate([dW1.ravel(), db1, dW2.ravel(), db2, dw3, [db3]]), loss
+
+
+def grad_envelope(P, T, draws: int = 16, seed: int = 0):
+    """Per-parameter spread of the gradient under FP16 operands: the largest
+    deviation from the FP16-rounded gradient over ``draws`` gradients whose
+    half-precision operands are each moved by up to one FP16 unit in the last
+    place (covering a rounding that lands on the other neighbour)."""
+    rng = np.random.default_rng(seed)
+    g0, _ = grad(P, T, half="fp16")
+    env = np.zeros_like(g0)
+    for _ in range(draws):
+        gp, _ = grad(P, T, half="perturb", rng=rng)
+        env = np.maximum(env, np.abs(gp - g0))
+    return g0, env
 
 
 def round_bf16(P):

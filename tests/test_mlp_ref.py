@@ -37,3 +37,21 @@ def test_activation_and_bf16_rounding():
     r = mlp_ref.round_bf16(x)
     assert list(r[[0, 1, 2, 3, 5]]) == [1.0, 1.0078125, 1.0, 1.015625, 0.0]
     assert abs(r[4] - x[4]) <= 2 ** -8 * abs(x[4])
+
+
+def test_fp16_reference_and_envelope():
+    # rounding the half-precision operands moves the gradient by a few FP16
+    # units relative; the envelope covers that move and is zero only where
+    # the gradient itself does not depend on a half-precision operand
+    rng = np.random.default_rng(1)
+    P = mlp_ref.round_bf16(rng.normal(0, 0.2, mlp_ref.N_PARAMS))
+    T = np.column_stack([rng.normal(0, 1, (256, 3)), rng.normal(0, 1, 256), rng.uniform(0, 1, 256)])
+    g, _ = mlp_ref.grad(P, T)
+    g16, env = mlp_ref.grad_envelope(P, T, draws=8)
+    scale = np.abs(g).max()
+    assert np.max(np.abs(g16 - g)) <= 2e-2 * scale
+    assert np.max(np.abs(g16 - g)) > 0.0
+    assert np.all(env >= 0) and np.max(env) <= 2e-2 * scale
+    # the rounding-free call is unchanged by the half-precision option's absence
+    g2, _ = mlp_ref.grad(P, T, half=None)
+    assert np.array_equal(g, g2)

@@ -234,8 +234,12 @@ def test_terms_hand_worked(orc, mode):
         rows = np.array([case["trial"]], dtype=np.int32)
         y, g, om, ye = orc.run_layer(lay, rows, [0], w["catalog_size"], seed=1, mode=mode, yelt=True)
         assert y[0] == case["Y"]
+        assert g[0] == case["gross"]                            # the scale of every per-trial tolerance
         assert om[0] == case["max_occ"]
         assert list(ye[0]) == case["yelt"]                      # per-occurrence losses (YELT)
+        inc = orc.yelt_increments(ye, lay.agg_retention, lay.agg_limit)
+        assert list(inc[0]) == case["increments"]               # aggregate increments, order-dependent
+        assert math.fsum(inc[0]) == case["Y"]                   # and they telescope to the year loss
 
 
 def test_risk_measures_hand_worked(orc):
