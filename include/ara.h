@@ -155,6 +155,36 @@ ara_status ara_run_layer_yelt(ara_ctx *ctx, int32_t yet_handle, const ara_layer_
                               float *ylt_out, float *max_occ_out, float *yelt_out, void *hip_stream);
 
 /*
+ * Per-occurrence aggregate increments (section 2.3 applies the aggregate terms
+ * to the cumulative sum of a trial's occurrence losses, so each occurrence's
+ * share of the year loss depends on the events before it; section 2.4 lists
+ * per-occurrence reports among the outputs).  yelt holds, in the layout
+ * ara_run_layer_yelt writes for trials [trial_begin, trial_end), each
+ * occurrence's loss o_k net of XELT and occurrence terms.  With S_k the sum of
+ * the trial's o_0..o_k (FP64) and A_k = min(max(S_k - agg_retention, 0),
+ * agg_limit), inc_out[same index] = A_k - A_{k-1} (A_{-1} = 0), rounded to
+ * FP32: the increments of a trial add up to its year loss, and unlike the
+ * year loss they depend on the order of its events.  yelt and inc_out: float,
+ * both device (asynchronous on hip_stream) or both host (synchronous).
+ * agg_retention >= 0 and finite, agg_limit >= 0 (+inf allowed); ARA_E_INVAL
+ * otherwise.
+ */
+ara_status ara_yelt_increments(ara_ctx *ctx, int32_t yet_handle, int64_t trial_begin, int64_t trial_end,
+                               double agg_retention, double agg_limit, const float *yelt, float *inc_out,
+                               void *hip_stream);
+
+/*
+ * The Beta parameters a loaded XELT's entries were given on the device at load
+ * time (section 3.3: mu_beta = mean/max_l, sigma_beta = min(sigma/max_l,
+ * 0.999 sigma_beta_max), nu = (sigma_beta_max/sigma_beta)^2 - 1,
+ * alpha = mu_beta nu, beta = (1 - mu_beta) nu, all in FP64).  alpha_out,
+ * beta_out: host, n_entries doubles each, in the XELT's entry order; both are
+ * 0 for an entry with sigma_I + sigma_C = 0 (its loss is the mean).
+ * Synchronous.
+ */
+ara_status ara_elt_params(ara_ctx *ctx, int32_t elt_handle, double *alpha_out, double *beta_out);
+
+/*
  * A batch of layers over one YET in one launch: each trial tile's event ids
  * are read from HBM once and evaluated for every layer.  ylt_outs[l] receives
  * layer l's YLT (device pointers only).
@@ -249,8 +279,10 @@ ara_status ara_last_kernel_ms(ara_ctx *ctx, double *ms_out);
  * Model: x = sigmoid(m + s v + NN(ln a / 2, ln b / 2, v / 3)) with v = Phi^-1(u),
  * m = psi(a) - psi(b), s = sqrt(psi'(a) + psi'(b)) (the logit-normal
  * approximation of the Beta quantile) and NN a 3 -> 64 -> 64 -> 1 perceptron
- * with activation z sigmoid(1.702 z), BF16 weights, FP16 activations and FP32
- * accumulation on the matrix cores.  Domain: a, b in [0.2, 50].  A table over
+ * with the GELU-like activation g(z) = z S(z), S(z) = w^2 (3 - 2w),
+ * w = clamp(z/5 + 1/2, 0, 1) (a cubic gate in place of the Gaussian CDF),
+ * weights rounded to BF16 and evaluated as FP16, FP16 activations and FP32
+ * accumulation on the matrix cores (v_mfma_f32_16x16x32_f16).  Domain: a, b in [0.2, 50].  A table over
  * 16 x 16 x 16 cells of (ln a, ln b, v) holds the largest absolute error in x
  * seen on held-out points; draws outside the domain or in a cell whose bound
  * exceeds the tolerance use the plain inverse.
@@ -266,9 +298,10 @@ ara_status ara_last_kernel_ms(ara_ctx *ctx, double *ms_out);
  * Training clears the region table (bias and fallback marks).
  * ara_surrogate_calibrate: fills the region table from n_val fresh held-out
  * tuples: each cell's mean signed error becomes its bias, which inference
- * subtracts from x, and cells whose largest error after that correction
- * exceeds tol (or that saw no point) are marked for fallback to the exact
- * inverse.  Outputs (optional, host): per-cell largest |error| after the
+ * subtracts from x, and cells whose largest error after that correction,
+ * times a margin of 1.5, exceeds tol, or that saw fewer than 64 points, are
+ * marked for fallback to the exact inverse.  The table is a deterministic
+ * function of the weights, n_val and seed.  Outputs (optional, host): per-cell largest |error| after the
  * correction and the bias (float [4096] each), number of marked cells.
  * ara_surrogate_grad: loss and gradient (float [4481], host) of the mean
  * squared error over n host tuples (f0, f1, f2, base, x; n a multiple of 64,

@@ -93,6 +93,8 @@ def lib() -> C.CDLL:
             "ara_beta_quantile": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_beta_quantile_layer": (i32, [vp, vp, vp, vp, i64, vp, vp]),
             "ara_beta_quantile_table": (i32, [vp, vp, vp, vp, i64, vp, vp]),
+            "ara_yelt_increments": (i32, [vp, i32, i64, i64, d, d, vp, vp, vp]),
+            "ara_elt_params": (i32, [vp, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -236,6 +238,29 @@ def ara_run_layer_yelt(ctx, yet_handle: int, layer: LayerDesc, mode: int, seed: 
     _check(ctx, lib().ara_run_layer_yelt(ctx, int(yet_handle), C.byref(layer), int(mode), int(seed) & 0xFFFFFFFF,
                                          int(trial_begin), int(trial_end), _ptr(ylt_out), _ptr(max_occ_out),
                                          _ptr(yelt_out), _stream(stream, ylt_out, max_occ_out, yelt_out)))
+
+
+def ara_yelt_increments(ctx, yet_handle: int, trial_begin: int, trial_end: int, agg_retention: float,
+                        agg_limit: float, yelt, inc_out=None, stream=None):
+    """Per-occurrence aggregate increments A_k - A_{k-1} of a YELT (same layout)."""
+    if isinstance(yelt, np.ndarray):
+        yelt = np.ascontiguousarray(yelt, dtype=np.float32)
+        if inc_out is None:
+            inc_out = np.empty_like(yelt)
+    elif inc_out is None:
+        inc_out = yelt.new_empty(yelt.shape)
+    _check(ctx, lib().ara_yelt_increments(ctx, int(yet_handle), int(trial_begin), int(trial_end),
+                                          float(agg_retention), float(agg_limit), _ptr(yelt), _ptr(inc_out),
+                                          _stream(stream, yelt, inc_out)))
+    return inc_out
+
+
+def ara_elt_params(ctx, elt_handle: int, n_entries: int):
+    """(alpha, beta) of each entry of a loaded XELT, as the device derived them (0, 0 if degenerate)."""
+    a = np.empty(int(n_entries))
+    b = np.empty(int(n_entries))
+    _check(ctx, lib().ara_elt_params(ctx, int(elt_handle), a.ctypes.data, b.ctypes.data))
+    return a, b
 
 
 def ara_normal_quantile(ctx, p) -> np.ndarray:

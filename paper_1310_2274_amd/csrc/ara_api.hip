@@ -99,6 +99,11 @@ struct ara_ctx {
     bool profiling = false;
     bool have_timing = false;
     hipEvent_t k_start = nullptr, k_stop = nullptr;
+    // Freed device blocks kept for reuse: hipFree waits for the whole device,
+    // so the context hands memory back to HIP only when its budget or the
+    // pool cap needs it, or on ara_destroy.
+    std::vector<DevBuf> pool;
+    uint64_t pooled = 0;
 };
 
 namespace {
@@ -124,15 +129,55 @@ ara_status fail(ara_ctx* c, ara_status st, const char* fmt, ...)
             return fail(ctx, ARA_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
     } while (0)
 
+// Pooled blocks are reused by later calls only.  Every call starts behind the
+// previous call's last event (begin_call) or on the same stream, so a block a
+// kernel may still read is never written before that kernel is done.
+constexpr uint64_t kPoolCap = (uint64_t)8 << 30;
+
+void pool_release(ara_ctx* c, size_t i)
+{
+    (void)hipFree(c->pool[i].p);
+    c->pooled -= c->pool[i].bytes;
+    c->pool.erase(c->pool.begin() + (std::ptrdiff_t)i);
+}
+
+void pool_release_largest(ara_ctx* c)
+{
+    size_t big = 0;
+    for (size_t i = 1; i < c->pool.size(); ++i)
+        if (c->pool[i].bytes > c->pool[big].bytes) big = i;
+    pool_release(c, big);
+}
+
 ara_status dev_alloc(ara_ctx* c, DevBuf& b, size_t bytes)
 {
-    if (bytes == 0) bytes = 256;
+    bytes = bytes == 0 ? 256 : (bytes + 255) & ~(size_t)255;
+    // the smallest pooled block that fits without wasting more than a quarter of it
+    size_t best = c->pool.size();
+    for (size_t i = 0; i < c->pool.size(); ++i) {
+        const size_t sz = c->pool[i].bytes;
+        if (sz >= bytes && sz - bytes <= sz / 4 && (best == c->pool.size() || sz < c->pool[best].bytes)) best = i;
+    }
+    if (best < c->pool.size()) {
+        b = c->pool[best];
+        c->pool.erase(c->pool.begin() + (std::ptrdiff_t)best);
+        c->pooled -= b.bytes;
+        c->used += b.bytes;
+        return ARA_OK;
+    }
+    while (c->budget && c->used + c->pooled + bytes > c->budget && !c->pool.empty()) pool_release_largest(c);
     if (c->budget && c->used + bytes > c->budget)
         return fail(c, ARA_E_BUDGET, "HBM budget exceeded: %llu in use + %llu requested > %llu",
                     (unsigned long long)c->used, (unsigned long long)bytes, (unsigned long long)c->budget);
     hipError_t e = hipMalloc(&b.p, bytes);
+    if (e == hipErrorOutOfMemory && !c->pool.empty()) {
+        (void)hipGetLastError();
+        while (!c->pool.empty()) pool_release(c, c->pool.size() - 1);
+        e = hipMalloc(&b.p, bytes);
+    }
     if (e == hipErrorOutOfMemory) {
         (void)hipGetLastError();
+        b.p = nullptr;
         return fail(c, ARA_E_BUDGET, "device out of memory allocating %llu bytes", (unsigned long long)bytes);
     }
     if (e != hipSuccess) return fail(c, ARA_E_DEVICE, "hipMalloc: %s", hipGetErrorString(e));
@@ -141,21 +186,23 @@ ara_status dev_alloc(ara_ctx* c, DevBuf& b, size_t bytes)
     return ARA_OK;
 }
 
+// Return a block to the context's pool (no device synchronisation).
 void dev_free(ara_ctx* c, DevBuf& b)
 {
     if (b.p) {
-        (void)hipFree(b.p);
         c->used -= b.bytes;
+        c->pool.push_back(b);
+        c->pooled += b.bytes;
+        while (c->pooled > kPoolCap && c->pool.size() > 1) pool_release(c, 0);   // oldest first
     }
     b.p = nullptr;
     b.bytes = 0;
 }
 
-// Grow-only workspace: the old buffer is released only after the device is idle.
+// Grow-only workspace; the old block goes back to the pool.
 ara_status ws_reserve(ara_ctx* c, DevBuf& b, size_t bytes)
 {
     if (b.bytes >= bytes) return ARA_OK;
-    HIPCHK(c, hipDeviceSynchronize());
     dev_free(c, b);
     return dev_alloc(c, b, bytes + bytes / 8);
 }
@@ -391,7 +438,6 @@ ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
                                     (uint32_t*)scratch.p, s));
     HIPCHK(c, launch_yet_slice_scatter(yd, (const uint32_t*)y.soff.p, (const uint32_t*)y.scnt.p, (int32_t*)y.sev.p,
                                        s));
-    HIPCHK(c, hipStreamSynchronize(s));
     dev_free(c, scratch);
     return ARA_OK;
 }
@@ -663,6 +709,15 @@ void ara_destroy(ara_ctx* c)
         dev_free(c, e.mean);
     }
     for (auto& pl : c->prepared) dev_free(c, pl.mem);
+    for (auto& y : c->yets) {
+        dev_free(c, y.sev);
+        dev_free(c, y.soff);
+        dev_free(c, y.scnt);
+    }
+    for (auto& e : c->elts) {
+        dev_free(c, e.sol);
+        dev_free(c, e.tab);
+    }
     dev_free(c, c->ws_tab);
     dev_free(c, c->ws_out);
     dev_free(c, c->ws_sel);
@@ -671,6 +726,7 @@ void ara_destroy(ara_ctx* c)
     for (DevBuf* b : {&c->sur_P, &c->sur_m, &c->sur_v, &c->sur_grad, &c->sur_frag, &c->sur_mask, &c->sur_bias, &c->sur_loss,
                       &c->sur_tuples, &c->sur_gpart, &c->sur_lpart, &c->sur_calib})
         dev_free(c, *b);
+    while (!c->pool.empty()) pool_release(c, c->pool.size() - 1);
     for (auto& sl : c->stage) {
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.dev) (void)hipFree(sl.dev);
@@ -685,7 +741,7 @@ void ara_destroy(ara_ctx* c)
 
 const char* ara_last_error(const ara_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-uint64_t ara_bytes_in_use(const ara_ctx* c) { return c ? c->used : 0; }
+uint64_t ara_bytes_in_use(const ara_ctx* c) { return c ? c->used + c->pooled : 0; }
 
 ara_status ara_load_yet(ara_ctx* c, const int32_t* event_ids, const int64_t* trial_offsets, int64_t n_trials,
                         int32_t events_per_trial, int32_t catalog_size, int32_t* yet_handle)
@@ -755,7 +811,6 @@ ara_status ara_free_yet(ara_ctx* c, int32_t h)
 {
     if (!c) return ARA_E_STATE;
     if (h < 0 || h >= (int32_t)c->yets.size() || !c->yets[h].live) return fail(c, ARA_E_STATE, "unknown YET %d", h);
-    HIPCHK(c, hipDeviceSynchronize());
     dev_free(c, c->yets[h].ev);
     dev_free(c, c->yets[h].offs);
     dev_free(c, c->yets[h].sev);
@@ -860,7 +915,6 @@ ara_status ara_free_elts(ara_ctx* c, const int32_t* h, int32_t n)
     for (int i = 0; i < n; ++i)
         if (h[i] < 0 || h[i] >= (int32_t)c->elts.size() || !c->elts[h[i]].live)
             return fail(c, ARA_E_STATE, "unknown XELT handle %d", h[i]);
-    HIPCHK(c, hipDeviceSynchronize());
     for (int i = 0; i < n; ++i) {
         EltRec& e = c->elts[h[i]];
         dev_free(c, e.idx);
@@ -902,6 +956,63 @@ ara_status ara_run_layer_yelt(ara_ctx* c, int32_t yh, const ara_layer_desc* laye
     float* om[1] = {max_occ_out};
     float* ye[1] = {yelt_out};
     return run_impl(c, yh, layer, 1, mode, seed, trial_begin, trial_end, outs, om, ye, hip_stream, true);
+}
+
+ara_status ara_yelt_increments(ara_ctx* c, int32_t yh, int64_t t0, int64_t t1, double agg_retention,
+                               double agg_limit, const float* yelt, float* inc_out, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (yh < 0 || yh >= (int32_t)c->yets.size() || !c->yets[yh].live) return fail(c, ARA_E_STATE, "unknown YET %d", yh);
+    YetRec& y = c->yets[yh];
+    if (t0 < 0 || t1 > y.N || t0 > t1) return fail(c, ARA_E_RANGE, "trial range [%lld, %lld) outside [0, %lld)",
+                                                   (long long)t0, (long long)t1, (long long)y.N);
+    if (!yelt || !inc_out) return fail(c, ARA_E_INVAL, "yelt and inc_out must not be NULL");
+    if (!(agg_retention >= 0.0) || !is_finite(agg_retention) || !(agg_limit >= 0.0))
+        return fail(c, ARA_E_INVAL, "aggregate terms must be >= 0 (retention finite)");
+    const bool din = is_device_ptr(yelt), dout = is_device_ptr(inc_out);
+    if (din != dout) return fail(c, ARA_E_INVAL, "yelt and inc_out must both be device or both host memory");
+    const int64_t r0 = y.hoffs.empty() ? t0 * (int64_t)y.K : y.hoffs[(size_t)t0];
+    const int64_t r1 = y.hoffs.empty() ? t1 * (int64_t)y.K : y.hoffs[(size_t)t1];
+    const size_t n = (size_t)(r1 - r0);
+    hipStream_t s = pick_stream(c, hip_stream);
+    ara_status st = begin_call(c, s);
+    if (st) return st;
+    const float* occ = yelt;
+    float* inc = inc_out;
+    if (!din) {
+        if ((st = ws_reserve(c, c->ws_out, 2 * align256(n * 4)))) return st;
+        float* in_dev = (float*)c->ws_out.p;
+        inc = (float*)((char*)c->ws_out.p + align256(n * 4));
+        if (n) HIPCHK(c, hipMemcpyAsync(in_dev, yelt, n * 4, hipMemcpyHostToDevice, s));
+        occ = in_dev;
+    }
+    YetDev yd{(const int32_t*)y.ev.p, (const int64_t*)y.offs.p, y.N, y.K, y.C};
+    HIPCHK(c, launch_yelt_increments(yd, t0, t1, r0, agg_retention, agg_limit, occ, inc, s));
+    if (!din && n) HIPCHK(c, hipMemcpyAsync(inc_out, inc, n * 4, hipMemcpyDeviceToHost, s));
+    if ((st = end_call(c, s))) return st;
+    if (!din) HIPCHK(c, hipStreamSynchronize(s));
+    return ARA_OK;
+}
+
+ara_status ara_elt_params(ara_ctx* c, int32_t h, double* alpha_out, double* beta_out)
+{
+    if (!c) return ARA_E_STATE;
+    if (h < 0 || h >= (int32_t)c->elts.size() || !c->elts[h].live)
+        return fail(c, ARA_E_STATE, "unknown XELT handle %d", h);
+    if (!alpha_out || !beta_out) return fail(c, ARA_E_INVAL, "alpha_out and beta_out must not be NULL");
+    const EltRec& e = c->elts[h];
+    ara_status st = begin_call(c, c->stream);
+    if (st) return st;
+    std::vector<EntryRec> host((size_t)e.n);
+    if (e.n) HIPCHK(c, hipMemcpyAsync(host.data(), e.ent.p, (size_t)e.n * sizeof(EntryRec), hipMemcpyDeviceToHost,
+                                      c->stream));
+    if ((st = end_call(c, c->stream))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int32_t r = 0; r < e.n; ++r) {
+        alpha_out[r] = host[(size_t)r].a;     // 0 marks a degenerate entry (sigma = 0)
+        beta_out[r] = host[(size_t)r].a == 0.0 ? 0.0 : host[(size_t)r].b;
+    }
+    return ARA_OK;
 }
 
 ara_status ara_run_layers(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_t n_layers, ara_mode mode,
@@ -958,7 +1069,6 @@ ara_status ara_free_layer(ara_ctx* c, int32_t h)
     if (!c) return ARA_E_STATE;
     if (h < 0 || h >= (int32_t)c->prepared.size() || !c->prepared[h].live)
         return fail(c, ARA_E_STATE, "unknown prepared layer %d", h);
-    HIPCHK(c, hipDeviceSynchronize());
     dev_free(c, c->prepared[h].mem);
     c->prepared[h].live = false;
     return ARA_OK;
@@ -1304,11 +1414,11 @@ ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, dou
     const size_t cb = (size_t)kCells * (4 + 8 + 4);
     if ((st = ws_reserve(c, c->sur_calib, cb))) return st;
     unsigned int* cnt = (unsigned int*)c->sur_calib.p;
-    double* sum = (double*)((char*)c->sur_calib.p + kCells * 4);
+    unsigned long long* sum = (unsigned long long*)((char*)c->sur_calib.p + kCells * 4);
     unsigned int* mx = (unsigned int*)((char*)c->sur_calib.p + kCells * 12);
     HIPCHK(c, sur_launch_build_frag((const float*)c->sur_P.p, (MlpFrag*)c->sur_frag.p, nullptr));
     std::vector<unsigned int> hc(kCells), hm(kCells);
-    std::vector<double> hs(kCells);
+    std::vector<long long> hs(kCells);
     std::vector<float> bias(kCells, 0.0f);
     // pass 1: each region's mean error; pass 2: the largest error left after
     // subtracting it (the bias the layer kernel applies)
@@ -1320,7 +1430,7 @@ ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, dou
         HIPCHK(c, hipMemcpy(hs.data(), sum, kCells * 8, hipMemcpyDeviceToHost));
         HIPCHK(c, hipMemcpy(hm.data(), mx, kCells * 4, hipMemcpyDeviceToHost));
         if (pass == 0) {
-            for (int i = 0; i < kCells; ++i) bias[i] = hc[i] ? (float)(hs[i] / hc[i]) : 0.0f;
+            for (int i = 0; i < kCells; ++i) bias[i] = hc[i] ? (float)((double)hs[i] / kCalibScale / hc[i]) : 0.0f;
             HIPCHK(c, hipMemcpy(c->sur_bias.p, bias.data(), kCells * 4, hipMemcpyHostToDevice));
         }
     }
@@ -1329,7 +1439,7 @@ ara_status ara_surrogate_calibrate(ara_ctx* c, int64_t n_val, uint32_t seed, dou
     for (int i = 0; i < kCells; ++i) {
         float m;
         std::memcpy(&m, &hm[i], 4);
-        const bool bad = hc[i] == 0 || (double)m > tol;
+        const bool bad = hc[i] < kCalibMinCount || kCalibMargin * (double)m > tol;
         if (bad) {
             bits[i >> 5] |= 1u << (i & 31);
             ++marked;

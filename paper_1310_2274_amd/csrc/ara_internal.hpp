@@ -9,7 +9,7 @@ namespace ara {
 constexpr int kMaxEltsPerLayer = 64;
 constexpr int kModeTable = 3;              // ARA_MODE_TABLE: the layer kernel's tabulated-inverse variant
 constexpr int kMaxRp = 16;
-constexpr float kSigmaClamp = 0.999f;      // sigma_beta <= 0.999 * sigma_beta_max
+constexpr double kSigmaClamp = 0.999;      // sigma_beta <= 0.999 * sigma_beta_max (applied in FP64)
 
 struct SurEntry;
 struct MlpFrag;
@@ -94,6 +94,10 @@ hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const 
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
                        const int32_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
                        hipStream_t s);
+// Per-occurrence aggregate increments of trials [t0, t1): occ and inc hold
+// the trials' occurrences from row `base` of the YET on.
+hipError_t launch_yelt_increments(const YetDev& y, int64_t t0, int64_t t1, int64_t base, double aggR, double aggL,
+                                  const float* occ, float* inc, hipStream_t s);
 hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, int64_t t1,
                          const LayerDev* layers, int32_t n_layers, int32_t wpb, hipStream_t s);
 

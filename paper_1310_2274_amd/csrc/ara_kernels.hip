@@ -43,7 +43,7 @@ __global__ void k_elt_prepare(int32_t n, const double* __restrict__ mean, const 
     } else {
         const double mub = mu / mx;                             // mu_beta
         const double sbmax = sqrt(mub * (1.0 - mub));           // sigma_beta_max
-        const double sb = fmin(s / mx, (double)kSigmaClamp * sbmax);
+        const double sb = fmin(s / mx, kSigmaClamp * sbmax);
         const double nu = (sbmax / sb) * (sbmax / sb) - 1.0;
         E.a = mub * nu;
         E.b = (1.0 - mub) * nu;
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                             QV[q] = kDeferred;
                         } else {
                             L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
-                            if (HAS_CORR) QV[q] = (float)zc;          // the FP32 solve takes z in FP32
+                            if (HAS_CORR) QV[q] = tail_code(zc);      // the FP32 solve takes z as its tail code
                         }
                     }
                     n32 = __builtin_amdgcn_readfirstlane(n32 + __popcll(b32));
@@ -471,14 +471,15 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         const int q = L32[idx];
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
+                        // uncorrelated draws are on the 2^-24 grid; correlated ones arrive as tail codes
                         const float z = HAS_CORR ? QV[q] : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
                         float loss;
                         if (TAB) {
                             const TabRec& T = L.ptab[pi];
-                            loss = T.maxl * tab_inverse(z, T);
+                            loss = T.maxl * (HAS_CORR ? tab_inverse_code(z, T) : tab_inverse(z, T));
                         } else {
                             const SolveRec& R = L.psol[pi];
-                            loss = R.maxl * inv_beta32(z, R);
+                            loss = R.maxl * (HAS_CORR ? inv_beta32_code(z, R) : inv_beta32(z, R));
                         }
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);                  // per-XELT terms
@@ -727,6 +728,42 @@ __global__ __launch_bounds__(256) void k_mean_yelt(YetDev y, int64_t t0, int64_t
         L.yelt[r - L.yelt_base] = L.occ_tab[y.ev[r]];
 }
 
+// Per-occurrence aggregate increments (section 2.3 applies the aggregate terms
+// to the running sum of a trial's occurrence losses, so each occurrence's
+// share of the year loss depends on the events before it).  With S_k the sum
+// of the trial's occurrence losses up to and including occurrence k (FP64)
+// and A_k = min(max(S_k - AggR, 0), AggL), occurrence k's increment is
+// A_k - A_{k-1} (A_{-1} = 0); the increments of a trial add up to A of its
+// last occurrence, its year loss.  One wavefront per trial, 64 occurrences
+// at a time through an FP64 wave prefix sum.
+__global__ __launch_bounds__(256) void k_yelt_increments(YetDev y, int64_t t0, int64_t t1, int64_t base, double aggR,
+                                                         double aggL, const float* __restrict__ occ,
+                                                         float* __restrict__ inc)
+{
+    const int lane = lane_id();
+    const int64_t trial = t0 + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (trial >= t1) return;
+    int64_t row;
+    int32_t len;
+    trial_range(y, trial, row, len);
+    double carry = 0.0, aprev = 0.0;          // S and A before the chunk
+    for (int32_t k0 = 0; k0 < len; k0 += 64) {
+        const int32_t k = k0 + lane;
+        double v = k < len ? (double)occ[row + k - base] : 0.0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const double o = __shfl_up(v, d, 64);
+            if (lane >= d) v += o;
+        }
+        const double S = carry + v;
+        const double A = fmin(fmax(S - aggR, 0.0), aggL);
+        const double Ab = __shfl_up(A, 1, 64);
+        if (k < len) inc[row + k - base] = (float)(A - (lane == 0 ? aprev : Ab));
+        carry = __shfl(S, 63, 64);            // lanes past the trial's end add nothing
+        aprev = __shfl(A, 63, 64);
+    }
+}
+
 // Large catalogs: one wavefront per trial gathers the table through L2.
 __global__ __launch_bounds__(256) void k_mean_gather(YetDev y, int64_t t0, int64_t t1,
                                                      const LayerDev* __restrict__ layers, int32_t n_layers)
@@ -918,7 +955,7 @@ __global__ void k_beta_quantile_table(const double* __restrict__ a, const double
     E.us = (float)beta_inc_lower((E.a + 1.0) / (E.a + E.b + 2.0), E.a, E.b, E.lnB);
     E.maxl = 1.0f;
     const TabRec T = make_tab_rec(E);               // as the table mode holds it
-    x[i] = (double)tab_inverse((float)u[i], T);
+    x[i] = (double)tab_inverse_code(tail_code(u[i]), T);
 }
 
 hipError_t launch_beta_quantile_table(const double* a, const double* b, const double* u, int64_t n, double* x,
@@ -1121,6 +1158,15 @@ hipError_t launch_layers(int mode, bool has_corr, const YetDev& y, int64_t t0, i
         case 8: launch_layers_wpb<8>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
         default: launch_layers_wpb<4>(mode, has_corr, y, t0, t1, layers, n_layers, s); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_yelt_increments(const YetDev& y, int64_t t0, int64_t t1, int64_t base, double aggR, double aggL,
+                                  const float* occ, float* inc, hipStream_t s)
+{
+    if (t1 > t0)
+        hipLaunchKernelGGL(k_yelt_increments, dim3(nblocks(t1 - t0, 4)), dim3(256), 0, s, y, t0, t1, base, aggR, aggL,
+                           occ, inc);
     return hipGetLastError();
 }
 

@@ -512,15 +512,38 @@ __device__ inline float newton32(float y, bool lower, float A, float B, float ln
     return lower ? __expf(y) : -expm1f(y);
 }
 
+// A draw's z in FP64 (the correlated draws of section 3.2) as the FP32 solves
+// take it: z itself at or below 1/2, minus (1 - z) above, with 1 - z formed in
+// FP64 before rounding, so either tail keeps its relative accuracy in one
+// float (rounding z itself would turn any z above 1 - 2^-25 into 1).  Draws on
+// the 2^-24 grid code exactly.
+__host__ __device__ inline float tail_code(double z)
+{
+    return z <= 0.5 ? (float)z : -(float)(1.0 - z);
+}
+
+// The side of t_s a coded draw falls on (lower: z <= I_ts = us) and that
+// side's probability p (z on the lower side, 1 - z on the upper).
+__host__ __device__ inline void tail_side(float code, float us, bool& lower, float& p)
+{
+    if (code > 0.0f) {
+        lower = code <= us;
+        p = lower ? code : 1.0f - code;
+    } else {
+        const float q = -code;                 // 1 - z
+        lower = q >= 1.0f - us;
+        p = lower ? 1.0f - q : q;
+    }
+}
+
 // FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape),
 // started from the entry's table: inv_beta's log-space iteration with Halley's
-// correction and the hardware helpers above.  Device only.
-__device__ inline float inv_beta32(float z, const SolveRec& R)
+// correction and the hardware helpers above, given the draw's side and that
+// side's probability.  Device only.
+__device__ inline float inv_beta32_side(bool lower, float p, const SolveRec& R)
 {
-    const bool lower = z <= R.us;
     const float A = lower ? R.a : R.b;
     const float B = lower ? R.b : R.a;
-    const float p = lower ? z : 1.0f - z;                  // exact on the 2^-24 grid
     const float lnp = f32_ln(p);
     const float rA = f32_rcp(A);
     const float c0 = -(R.lnB + f32_ln(A));
@@ -531,18 +554,32 @@ __device__ inline float inv_beta32(float z, const SolveRec& R)
     return newton32<false>(fminf((lnp - c0) * rA + r, ymax), lower, A, B, lnp, c0, rA, ymax);
 }
 
+// The same for a draw on the 2^-24 grid (p = 1 - z is exact there).
+__device__ inline float inv_beta32(float z, const SolveRec& R)
+{
+    const bool lower = z <= R.us;
+    return inv_beta32_side(lower, lower ? z : 1.0f - z, R);
+}
+
+// The same for a coded draw (tail_code).
+__device__ inline float inv_beta32_code(float code, const SolveRec& R)
+{
+    bool lower;
+    float p;
+    tail_side(code, R.us, lower, p);
+    return inv_beta32_side(lower, p, R);
+}
+
 // The same solve started from a corrected leading term, for callers that hold
 // only the entry record.  ln I_t = A y + c0 + g(t) with g(t) = B ln(1-t) -
 // ln T(t), which vanishes at t = 0 and equals ln I_ts - A ln ts - c0 at ts (I_ts
 // is stored).  Taking g linear in t and evaluating it at the leading-term root
 // gives one cheap fixed-point step that brings the draws near ts, where the
 // leading term alone is worst, within one Newton step.  Device only.
-__device__ inline float inv_beta32(float z, const EntryRec& E)
+__device__ inline float inv_beta32_side(bool lower, float p, const EntryRec& E)
 {
-    const bool lower = z <= E.us;
     const float A = (float)(lower ? E.a : E.b);
     const float B = (float)(lower ? E.b : E.a);
-    const float p = lower ? z : 1.0f - z;
     const float lnp = f32_ln(p);
     const float rA = f32_rcp(A);
     const float c0 = -((float)E.lnB + f32_ln(A));
@@ -554,6 +591,14 @@ __device__ inline float inv_beta32(float z, const EntryRec& E)
     const float gs = lnps - A * lts - c0;
     y = fminf((lnp - c0 - gs * __expf(y) * f32_rcp(ts)) * rA, lts);
     return newton32<true>(y, lower, A, B, lnp, c0, rA, ymax);
+}
+
+__device__ inline float inv_beta32_code(float code, const EntryRec& E)
+{
+    bool lower;
+    float p;
+    tail_side(code, E.us, lower, p);
+    return inv_beta32_side(lower, p, E);
 }
 
 // ---------------------------------------------------------------------------
@@ -606,12 +651,10 @@ __host__ __device__ inline TabRec make_tab_rec(const EntryRec& E)
 
 // x = I^-1(z) from the entry's table (1 for a degenerate entry, whose loss is
 // maxl).
-__host__ __device__ inline float tab_inverse(float z, const TabRec& T)
+__host__ __device__ inline float tab_inverse_side(bool lower, float p, const TabRec& T)
 {
     if (T.deg) return 1.0f;
-    const bool lower = z <= T.us;
     const float A = lower ? T.a : T.b;
-    const float p = lower ? z : 1.0f - z;
     const float lnp = f32_ln(p);
     const float rA = f32_rcp(A);
     const float c0 = T.c0[lower ? 0 : 1];
@@ -630,11 +673,26 @@ __host__ __device__ inline float tab_inverse(float z, const TabRec& T)
     return lower ? f32_exp(y) : -expm1f(y);
 }
 
-// The inverse the plain layer kernel applies to one draw.
+// The same for a draw on the 2^-24 grid, and for a coded draw (tail_code).
+__host__ __device__ inline float tab_inverse(float z, const TabRec& T)
+{
+    const bool lower = z <= T.us;
+    return tab_inverse_side(lower, lower ? z : 1.0f - z, T);
+}
+__host__ __device__ inline float tab_inverse_code(float code, const TabRec& T)
+{
+    bool lower;
+    float p;
+    tail_side(code, T.us, lower, p);
+    return tab_inverse_side(lower, p, T);
+}
+
+// The inverse the plain layer kernel applies to one draw of z (FP64: any z in
+// (0, 1), not only the 2^-24 grid, reaches the FP32 solve as its tail code).
 __device__ inline double inv_beta_layer(double z, const EntryRec& E, const SolveRec& R)
 {
     if (R.pol) return inv_beta(z, E, nullptr, &R);
-    return (double)inv_beta32((float)z, R);
+    return (double)inv_beta32_code(tail_code(z), R);
 }
 
 // Sampled loss of one draw: max_l * InvCDF_beta(z; alpha, beta) (section 3.3).

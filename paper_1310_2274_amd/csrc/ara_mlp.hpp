@@ -14,9 +14,11 @@
 //   output    x = sigmoid(m + s v + o)
 // so the network learns a residual in logit space.  Weights are kept in FP32
 // (training master copy) and used rounded to BF16; activations are FP16 and
-// every product accumulates in FP32.  BF16 values are exact in FP16 (8-bit
-// significand inside an 11-bit one), so the MFMAs run in FP16 on the BF16
-// weights.
+// every product accumulates in FP32.  A BF16 value is exact in FP16 when its
+// magnitude lies in FP16's normal range [2^-14, 65504] (8-bit significand
+// inside an 11-bit one); the MFMAs run in FP16 on the BF16-rounded weights,
+// so a weight below 2^-14 lands on an FP16 subnormal, within 2^-25 of its
+// BF16 value (the tests check that trained weights stay below 65504).
 #pragma once
 
 #include "ara_math.hpp"
@@ -38,6 +40,13 @@ constexpr float kSurLo = 0.2f, kSurHi = 50.0f;
 constexpr int kCellsA = 16, kCellsB = 16, kCellsV = 16;
 constexpr int kCells = kCellsA * kCellsB * kCellsV;
 constexpr float kVLim = 5.5f;              // |Phi^-1(u)| < 5.34 on the 2^-24 grid
+// Calibration: per-cell error sums in units of 2^-36 (|error| <= 1, so 10^7
+// points stay below 2^63); a cell answers by the surrogate only when it saw at
+// least kCalibMinCount held-out points and kCalibMargin times its largest
+// error after the bias correction is within the tolerance.
+constexpr double kCalibScale = 68719476736.0;   // 2^36
+constexpr unsigned kCalibMinCount = 64;
+constexpr double kCalibMargin = 1.5;
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));

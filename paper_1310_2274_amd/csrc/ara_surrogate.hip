@@ -280,8 +280,10 @@ __global__ void k_build_frag(const float* __restrict__ P, MlpFrag* __restrict__ 
 
 // ===========================================================================
 // Inference for arbitrary (a, b, u): calibration of the region table and the
-// evaluation entry point share it.  Cell statistics: count, sum of errors,
-// max |error| (as float bits: non-negative floats order like integers).
+// evaluation entry point share it.  Cell statistics: count, sum of errors in
+// fixed point (kCalibScale units; integer sums do not depend on the order of
+// the atomic adds, so the table is reproducible), max |error| (as float bits:
+// non-negative floats order like integers).
 // ===========================================================================
 __device__ inline void copy_frag_to_lds(const MlpFrag* __restrict__ Fg, MlpFrag& Fs)
 {
@@ -292,7 +294,8 @@ __device__ inline void copy_frag_to_lds(const MlpFrag* __restrict__ Fg, MlpFrag&
 
 __global__ __launch_bounds__(256) void k_sur_calib(const float* __restrict__ tuples, int64_t n,
                                                    const MlpFrag* __restrict__ Fg, const float* __restrict__ bias,
-                                                   unsigned int* __restrict__ cnt, double* __restrict__ sum,
+                                                   unsigned int* __restrict__ cnt,
+                                                   unsigned long long* __restrict__ sum,
                                                    unsigned int* __restrict__ maxbits)
 {
     __shared__ MlpFrag F;
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(256) void k_sur_calib(const float* __restrict__ tup
     const float xh = sur_debias(1.0f / (1.0f + expf(-(base + o))), bias ? bias[c] : 0.0f);
     const float e = xh - xt;
     atomicAdd(&cnt[c], 1u);
-    atomicAdd(&sum[c], (double)e);
+    atomicAdd(&sum[c], (unsigned long long)llrint((double)e * kCalibScale));   // two's complement sum
     atomicMax(&maxbits[c], __float_as_uint(fabsf(e)));
 }
 
@@ -377,9 +380,9 @@ __global__ void k_sur_entries(const EntryRec* __restrict__ pent, int64_t n, SurE
 // ===========================================================================
 // The exact inverse for the draws the surrogate does not answer, out of line
 // so its registers stay out of the MLP kernel's allocation.
-static __device__ __attribute__((noinline)) float exact_loss32(float z, EntryRec E)
+static __device__ __attribute__((noinline)) float exact_loss32(float code, EntryRec E)
 {
-    return E.maxl * inv_beta32(z, E);
+    return E.maxl * inv_beta32_code(code, E);
 }
 static __device__ __attribute__((noinline)) float exact_loss64(double z, EntryRec E)
 {
@@ -475,7 +478,9 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const SurEntry SE = L.psur[pi];
                         if (SE.f0 >= flo && SE.f0 <= fhi && SE.f1 >= flo && SE.f1 <= fhi) {
                             const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                            const float v = normcdfinvf((float)z);
+                            // Phi^-1 of the draw from its tail code (1 - z formed in FP64 for correlated draws)
+                            const float zc = tail_code(z);
+                            const float v = zc > 0.0f ? normcdfinvf(zc) : -normcdfinvf(-zc);
                             const int cell = sur_cell(SE.f0, SE.f1, v);
                             is_sur = !((mask[cell >> 5] >> (cell & 31)) & 1u);
                             QV[q] = v;
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         const EntryRec E = L.pent[pi];
                         const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
-                        const float loss = exact_loss32((float)z, E);
+                        const float loss = exact_loss32(tail_code(z), E);
                         const float4 jt = L.jt[j];
                         QV[q] = jt.z * xl(loss, jt.x, jt.y);
                     }
@@ -639,7 +644,7 @@ hipError_t sur_launch_build_frag(const float* P, MlpFrag* F, hipStream_t s)
 }
 
 hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, const float* bias, unsigned int* cnt,
-                            double* sum, unsigned int* maxbits, hipStream_t s)
+                            unsigned long long* sum, unsigned int* maxbits, hipStream_t s)
 {
     if (n > 0)
         hipLaunchKernelGGL(k_sur_calib, dim3(grid_for(n, 256)), dim3(256), 0, s, tuples, n, F, bias, cnt, sum, maxbits);

@@ -13,7 +13,7 @@ hipError_t sur_launch_train_step(const float* tuples, int64_t n_tuples, int64_t 
                                  float* loss_acc, float lr, int64_t step, bool update, hipStream_t s);
 hipError_t sur_launch_build_frag(const float* P, MlpFrag* F, hipStream_t s);
 hipError_t sur_launch_calib(const float* tuples, int64_t n, const MlpFrag* F, const float* bias, unsigned int* cnt,
-                            double* sum, unsigned int* maxbits, hipStream_t s);
+                            unsigned long long* sum, unsigned int* maxbits, hipStream_t s);
 hipError_t sur_launch_eval(const double* a, const double* b, const double* u, int64_t n, const MlpFrag* F,
                            const uint32_t* mask, const float* bias, double* x, int32_t* used, hipStream_t s);
 

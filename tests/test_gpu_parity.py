@@ -86,7 +86,7 @@ def test_beta_quantile_paper_scale_parameters(eng):
     assert np.max(np.abs(x[visible] - xo[visible]) / xo[visible]) <= 1e-8
 
 
-@pytest.mark.parametrize("lo,hi,seed", [(1e-3, 40.0, 5), (0.2, 50.0, 6)])
+@pytest.mark.parametrize("lo,hi,seed", [(1e-3, 40.0, 5), (0.2, 50.0, 6), (3e-6, 35.0, 7)])
 def test_layer_inverse_per_draw_accuracy(eng, lo, hi, seed):
     # the inverse exactly as the plain layer kernel applies it: FP32 alone
     # where min(a, b) >= 0.2 (a few 1e-6 relative), FP32 + FP64 polish below
@@ -100,6 +100,62 @@ def test_layer_inverse_per_draw_accuracy(eng, lo, hi, seed):
     assert np.quantile(rel[visible & fp32], 0.99) <= 2e-6
     assert np.all(rel[visible & ~fp32] <= 1e-8)
     assert np.all(x[~visible] <= 1e-28)
+
+
+@pytest.mark.parametrize("side", ["upper", "lower"])
+def test_layer_inverse_off_grid_tails(eng, side):
+    # Correlated draws (section 3.2) give z = Phi(v) anywhere in (0, 1), not on
+    # the 2^-24 grid, and as close to 1 as 1 - 1e-13.  The layer's inverse must
+    # keep the tail's relative accuracy: with a large leading shape the
+    # quantile of a tail probability p is far from 0 or 1, so an error in p
+    # shows up in x (rounding z near 1 to FP32 would move p by up to 100%).
+    ks = np.arange(6, 14)
+    rng = np.random.default_rng(17)
+    n = 4000
+    k = rng.choice(ks, n)
+    tail = 10.0 ** (-k) * rng.uniform(1.0, 9.0, n)
+    big = np.exp(rng.uniform(math.log(5.0), math.log(35.0), n))
+    small = np.exp(rng.uniform(math.log(0.3), math.log(3.0), n))
+    small[::4] = np.exp(rng.uniform(math.log(1e-3), math.log(0.19), n // 4))   # the FP64 path too
+    if side == "upper":
+        a, b, u = small, big, 1.0 - tail
+    else:
+        a, b, u = big, small, tail
+    x = P.ara_beta_quantile_layer(eng.ctx, a, b, u)
+    xo = oracle.beta_inc_inv_vec(u, a, b, threads=0)
+    dist = np.minimum(xo, 1.0 - xo)          # distance from the nearer end of [0, 1]
+    fp32 = np.minimum(a, b) >= 0.2
+    err = np.abs(x - xo)
+    # FP32 solve: 1e-5 of that distance, or FP32's spacing next to 1
+    assert np.all(err[fp32] <= 1e-5 * dist[fp32] + 1.2e-7), (err[fp32] / (dist[fp32] + 1e-30)).max()
+    assert np.all(err[~fp32] <= 1e-8 * dist[~fp32] + 1e-15)
+    assert np.median(dist) > 1e-3            # the cases exercise quantiles away from the ends
+
+
+def test_clamped_entries_beta_params_match_oracle(eng):
+    # Section 3.3's moment matching with the std bound: entries whose std
+    # exceeds c * sigma_beta_max (c = 0.999) are clamped to it.  The device's
+    # FP64 alpha, beta against the oracle's, clamped or not.
+    rng = np.random.default_rng(23)
+    n = 3000
+    mu = rng.lognormal(10, 1.5, n)
+    mx = mu * rng.uniform(1.05, 10, n)
+    mub = mu / mx
+    sbmax = np.sqrt(mub * (1 - mub)) * mx
+    sd = sbmax * rng.uniform(0.05, 3.0, n)                 # about two thirds are clamped
+    sd[:5] = sbmax[:5] * np.array([0.999, 0.99899, 0.99901, 1.0, 100.0])
+    sd[5] = 0.0                                            # degenerate entry
+    elt = synth.ELT(np.arange(n, dtype=np.int32), mu, sd, None, mx, 0.0, math.inf, 1.0)
+    h = P.ara_load_elts(eng.ctx, n, [elt])[0]
+    a, b = P.ara_elt_params(eng.ctx, h, n)
+    ref = np.array([oracle.beta_params(m, s, x)[:2] if s > 0 else (0.0, 0.0) for m, s, x in zip(mu, sd, mx)])
+    clamped = sd > 0.999 * sbmax
+    assert 1000 < clamped.sum() < n
+    np.testing.assert_allclose(a, ref[:, 0], rtol=2e-15, atol=0)
+    np.testing.assert_allclose(b, ref[:, 1], rtol=2e-15, atol=0)
+    nu = 1 / 0.999 ** 2 - 1
+    np.testing.assert_allclose(a[clamped], mub[clamped] * nu, rtol=1e-12)
+    P.ara_free_elts(eng.ctx, [h])
 
 
 def test_normal_quantile_vs_oracle_and_tables(eng):

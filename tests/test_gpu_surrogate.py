@@ -1,6 +1,9 @@
-"""GPU tests of the sampling surrogate: MFMA gradients against the FP64
+"""GPU tests of the sampling surrogate (a fast method for the inverse-Beta step
+of section 3.3): MFMA gradients element by element against the FP64
 reference, labels of the training tuples, trained error bounds with fallback,
-checkpointing, and the surrogate layer kernel against the oracle."""
+what the network gains over its logit-normal base, checkpointing, and the
+surrogate layer kernel (plain and correlated) against the FP64 oracle down to
+PML/TVaR (section 2.4)."""
 import math
 
 import numpy as np
@@ -15,6 +18,12 @@ from gpu_helpers import gpu_ylt, oracle_ylt, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
+# The surrogate's stated criterion: PML and TVaR within 1e-3 relative of the
+# FP64 oracle; per draw, |x - x_oracle| <= 1e-3 where the surrogate answers.
+PML_TVAR_REL = 1e-3
+DRAW_TOL = 1e-3
+RPS = (10.0, 50.0, 100.0, 250.0)
+
 
 @pytest.fixture(scope="module")
 def eng():
@@ -22,6 +31,32 @@ def eng():
     e = P.Engine(0)
     yield e
     e.close()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """A surrogate trained and calibrated in a context of its own; each test
+    imports this state, so no test depends on another having run first."""
+    torch_cuda()
+    with P.Engine(0) as e:
+        losses = P.ara_surrogate_train(e.ctx, 1_048_576, epochs=4, batch=4096, lr=3e-3, seed=11)
+        cmax, cbias, marked = P.ara_surrogate_calibrate(e.ctx, 2_000_000, seed=12, tol=DRAW_TOL)
+        state = P.ara_surrogate_export(e.ctx)
+    return {"losses": losses, "cmax": cmax, "cbias": cbias, "marked": marked, "state": state}
+
+
+def _import(ctx, st, **override):
+    s = dict(st)
+    s.update(override)
+    P.ara_surrogate_import(ctx, s["params"], s["adam_m"], s["adam_v"], s["step"], s["mask"], s["bias"])
+
+
+def _heldout(n, seed):
+    rng = np.random.default_rng(seed)
+    a = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
+    b = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
+    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    return a, b, u
 
 
 def test_training_tuples_features_and_labels(eng):
@@ -36,51 +71,65 @@ def test_training_tuples_features_and_labels(eng):
     assert np.median(np.abs(T[:, 4] - x)) < 1e-5 and np.quantile(np.abs(T[:, 4] - x), 0.99) < 1e-3
 
 
-def test_mfma_gradient_matches_fp64_reference(eng):
+def test_mfma_gradient_matches_fp64_reference_elementwise(eng):
+    # Every one of the 4481 gradient entries against the FP64 reference with
+    # the kernel's FP16 operands rounded the same way.  The tolerance of each
+    # entry is four times its spread when every FP16 operand moves by up to
+    # one unit in the last place (a rounding that lands on the other
+    # neighbour, FP32 vs FP64 accumulation before it), plus 1e-6 of the
+    # largest entry for FP32 accumulation.
     T = P.ara_surrogate_tuples(eng.ctx, 1024, seed=7)
-    # fresh weights: import a known random parameter vector
     rng = np.random.default_rng(3)
-    Pw = np.concatenate([rng.uniform(-0.3, 0.3, 192), np.zeros(64), rng.uniform(-0.2, 0.2, 4096), np.zeros(64),
-                         rng.uniform(-0.05, 0.05, 64), [0.0]]).astype(np.float32)
+    Pw = np.concatenate([rng.uniform(-0.3, 0.3, 192), rng.uniform(-0.1, 0.1, 64), rng.uniform(-0.2, 0.2, 4096),
+                         rng.uniform(-0.1, 0.1, 64), rng.uniform(-0.05, 0.05, 64), [0.01]]).astype(np.float32)
     P.ara_surrogate_import(eng.ctx, Pw)
     g, loss = P.ara_surrogate_grad(eng.ctx, T)
     Pq = mlp_ref.round_bf16(Pw)
     Tq = T.astype(np.float64)
     Tq[:, :3] = T[:, :3].astype(np.float16).astype(np.float64)
-    gr, lr = mlp_ref.grad(Pq, Tq)
+    g16, env = mlp_ref.grad_envelope(Pq, Tq, draws=24, seed=1)
+    _, lr = mlp_ref.grad(Pq, Tq, half="fp16")
     assert loss == pytest.approx(lr, rel=2e-3)
-    for name, lo, hi in [("W1", 0, 192), ("b1", 192, 256), ("W2", 256, 4352), ("b2", 4352, 4416),
-                         ("w3", 4416, 4480), ("b3", 4480, 4481)]:
-        d, r = g[lo:hi].astype(np.float64), gr[lo:hi]
-        rel = np.linalg.norm(d - r) / max(np.linalg.norm(r), 1e-30)
-        assert rel < 2e-2, (name, rel)
+    tol = 4.0 * env + 1e-6 * np.abs(g16).max()
+    err = np.abs(g.astype(np.float64) - g16)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, (bad[:10], err[bad[:10]], tol[bad[:10]])
+    print(f"gradient: max |err|/tol = {np.max(err / tol):.3f}, max |err| / max|g| = "
+          f"{err.max() / np.abs(g16).max():.2e}")
 
 
-def test_train_calibrate_and_error_bounds(eng, tmp_path):
-    losses = P.ara_surrogate_train(eng.ctx, 1_048_576, epochs=4, batch=4096, lr=3e-3, seed=11)
+def test_train_calibrate_and_error_bounds(eng, trained, tmp_path):
+    losses = trained["losses"]
     assert losses[-1] < losses[0] and np.isfinite(losses).all()
-    cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
+    cmax, cbias, marked = trained["cmax"], trained["cbias"], trained["marked"]
     assert 0 <= marked < P.SUR_CELLS
-    # fresh held-out points: where the table allows the surrogate, its error respects the bound
-    rng = np.random.default_rng(9)
-    n = 20000
-    a = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
-    b = np.exp(rng.uniform(math.log(0.2), math.log(50), n))
-    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    st = trained["state"]
+    _import(eng.ctx, st)
+    # the MFMAs take the BF16-rounded weights as FP16: exact inside FP16's
+    # normal range, within half an FP16 subnormal spacing (2^-25) below it
+    w = mlp_ref.round_bf16(st["params"])
+    w16 = w.astype(np.float16).astype(np.float64)
+    assert np.all(np.abs(w) <= 65504.0)
+    assert np.all(w16[np.abs(w) >= 2.0 ** -14] == w[np.abs(w) >= 2.0 ** -14])
+    assert np.max(np.abs(w16 - w)) <= 2.0 ** -25
+    a, b, u = _heldout(20000, 9)
     x, used = P.ara_surrogate_eval(eng.ctx, a, b, u)
     xo = oracle.beta_inc_inv_vec(u, a, b)
     err = np.abs(x - xo)
     assert np.all(err[used == 0] <= 1e-8 + 1e-8 * xo[used == 0])          # fallback is the plain inverse
-    if used.any():
-        # an empirical bound: allow a sliver of fresh points past it, none far past it
-        assert np.mean(err[used == 1] > 1e-3) < 2e-3
-        assert err[used == 1].max() < 5e-3
-        # the region bias is subtracted: what is left averages out
-        assert abs(np.mean((x - xo)[used == 1])) < 5e-5
+    assert used.mean() > 0.2                                                # the network answers a real share
+    # fresh held-out points in cells the table lets the surrogate answer
+    print(f"held-out: {used.sum()} surrogate answers, max err {err[used == 1].max():.2e}, "
+          f"share above {DRAW_TOL}: {np.mean(err[used == 1] > DRAW_TOL):.2e}")
+    assert np.all(err[used == 1] <= DRAW_TOL), err[used == 1].max()
+    assert abs(np.mean((x - xo)[used == 1])) < 5e-5                         # the region bias is subtracted
     assert np.all(np.isfinite(cbias)) and np.all(np.abs(cbias) <= 1) and np.all(cmax[cmax >= 0] >= 0)
     # outside the domain the plain inverse always answers
-    x2, used2 = P.ara_surrogate_eval(eng.ctx, np.array([0.1, 60.0]), np.array([1.0, 2.0]), np.array([0.3, 0.3]))
+    _, used2 = P.ara_surrogate_eval(eng.ctx, np.array([0.1, 60.0]), np.array([1.0, 2.0]), np.array([0.3, 0.3]))
     assert list(used2) == [0, 0]
+    # the region table is a deterministic function of the weights and the held-out seed
+    cmax2, cbias2, marked2 = P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=DRAW_TOL)
+    assert np.array_equal(cmax2, cmax) and np.array_equal(cbias2, cbias) and marked2 == marked
     # checkpoint round trip reproduces the same answers
     path = str(tmp_path / "sur.npz")
     P.save_surrogate(eng.ctx, path)
@@ -89,19 +138,66 @@ def test_train_calibrate_and_error_bounds(eng, tmp_path):
         x3, used3 = P.ara_surrogate_eval(e2.ctx, a[:512], b[:512], u[:512])
     assert np.array_equal(x3, x[:512]) and np.array_equal(used3, used[:512])
     print(f"surrogate: final loss {losses[-1]:.3e}, marked cells {marked}/{P.SUR_CELLS}, "
-          f"surrogate share {used.mean():.3f}, max err {err[used == 1].max() if used.any() else 0:.2e}, "
-          f"mean err {np.mean((x - xo)[used == 1]) if used.any() else 0:.2e}")
+          f"surrogate share {used.mean():.3f}, max err {err[used == 1].max():.2e}, "
+          f"mean err {np.mean((x - xo)[used == 1]):.2e}")
 
 
-def test_surrogate_layer_close_to_oracle(eng):
-    # after the training test: the surrogate layer stays within the surrogate's
-    # per-draw bound of the oracle, and matches the plain layer where it falls back
-    wl = synth.custom(256, 200, 3000, 6, 400, 1200, seed=19)
+def test_network_gains_over_its_base(eng, trained):
+    # The same held-out draws answered by the logit-normal base alone (output
+    # layer zeroed) and by base + trained network, both with no fallback.
+    st = trained["state"]
+    none = np.zeros(P.SUR_CELLS, dtype=np.uint8)
+    zero_bias = np.zeros(P.SUR_CELLS, dtype=np.float32)
+    a, b, u = _heldout(40000, 21)
+    xo = oracle.beta_inc_inv_vec(u, a, b)
+    base_params = st["params"].copy()
+    base_params[4416:] = 0.0                     # w3, b3: the network adds nothing
+    _import(eng.ctx, st, params=base_params, mask=none, bias=zero_bias)
+    xb, ub = P.ara_surrogate_eval(eng.ctx, a, b, u)
+    _import(eng.ctx, st, mask=none, bias=zero_bias)
+    xn, un = P.ara_surrogate_eval(eng.ctx, a, b, u)
+    assert ub.all() and un.all()
+    eb, en = np.abs(xb - xo), np.abs(xn - xo)
+    print(f"held-out |x - x_oracle|: base max {eb.max():.2e} mean {eb.mean():.2e}; "
+          f"base+MLP max {en.max():.2e} mean {en.mean():.2e}")
+    assert en.mean() < 0.1 * eb.mean()
+    assert en.max() < 0.5 * eb.max()
+    assert np.quantile(en, 0.99) < 0.1 * np.quantile(eb, 0.99)
+
+
+def _small_layer_case(sigma_c_frac=0.0, seed=31):
+    # 4,000 trials x 100 events, 4 ELTs: enough trials for the 250-year
+    # return period (k = 16), shapes mostly inside the surrogate's domain
+    return synth.custom(4000, 100, 2000, 4, 300, 700, seed=seed, sigma_c_frac=sigma_c_frac)
+
+
+@pytest.mark.parametrize("sigma_c_frac", [0.0, 0.6])
+def test_surrogate_layer_pml_tvar_vs_oracle(eng, trained, sigma_c_frac):
+    # The surrogate's end-to-end criterion on a layer: PML and TVaR of its YLT
+    # within 1e-3 relative of those of the FP64 oracle's YLT (section 2.4),
+    # uncorrelated and with correlated std (section 3.2's combined draws).
+    _import(eng.ctx, trained["state"])
+    wl = _small_layer_case(sigma_c_frac)
     y, _ = gpu_ylt(eng, wl, P.MODE_SURROGATE, 4)
     yo, g, _ = oracle_ylt(wl, np.arange(wl.n_trials), oracle.MODE_PLAIN, 4)
-    # every draw's loss error is at most 5e-3 * max_l <= 5e-3 * 10 * mean: bound by the gross loss
-    assert np.all(np.abs(y - yo) <= 0.05 * g + 1e-3)
     assert np.mean(np.abs(y - yo)) <= 2e-3 * np.mean(g)
+    pml, tvar = P.ara_risk_measures(eng.ctx, y.astype(np.float32), RPS)
+    po, to = oracle.risk_measures(yo, RPS)
+    rp, rt = np.abs(pml - po) / po, np.abs(tvar - to) / to
+    print(f"surrogate layer sigma_c_frac={sigma_c_frac}: PML rel err {rp.max():.2e}, TVaR rel err {rt.max():.2e}")
+    assert np.all(rp <= PML_TVAR_REL) and np.all(rt <= PML_TVAR_REL), (rp, rt)
     # deterministic
     y2, _ = gpu_ylt(eng, wl, P.MODE_SURROGATE, 4)
     assert np.array_equal(y, y2)
+
+
+def test_surrogate_layer_falls_back_to_the_plain_path(eng, trained):
+    # with every cell marked, the surrogate kernel answers every draw with the
+    # exact inverse: the plain layer's year losses within FP32 rounding
+    _import(eng.ctx, trained["state"], mask=np.ones(P.SUR_CELLS, dtype=np.uint8))
+    wl = synth.custom(300, 120, 1500, 5, 200, 500, seed=33, sigma_c_frac=0.5)
+    y, _ = gpu_ylt(eng, wl, P.MODE_SURROGATE, 8)
+    yp, _ = gpu_ylt(eng, wl, P.MODE_PLAIN, 8)
+    yo, g, _ = oracle_ylt(wl, np.arange(wl.n_trials), oracle.MODE_PLAIN, 8)
+    assert np.all(np.abs(y - yp) <= 1e-5 * g + 1e-3)
+    assert np.all(np.abs(y - yo) <= 1e-5 * g + 1e-3)

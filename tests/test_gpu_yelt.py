@@ -116,3 +116,98 @@ def test_occurrence_exceedance_risk_measures(eng):
     err = float(np.max(REL_TOL * g + ABS_TOL))
     assert np.all(np.abs(np.asarray(pml) - po) <= err) and np.all(np.abs(np.asarray(tvar) - to) <= err)
     assert np.all(np.asarray(pml) > 0)
+
+
+# ------------------------------------------------------------ F1: aggregate increments per occurrence
+def _w1_layer_gpu(eng, over):
+    from conftest import golden
+    w = golden("w1_terms.json")
+    elts = []
+    for e in w["elts"]:
+        m = np.array(e["mean"], dtype=float)
+        elts.append(synth.ELT(np.array(e["event_id"], dtype=np.int32), m, np.zeros_like(m), None, m * 4,
+                              e["deductible"], e["limit"], e["share"]))
+    t = dict(w["layer"])
+    t.update(over)
+    return w, synth.Layer(elts, t["occ_retention"], t["occ_limit"], t["agg_retention"], t["agg_limit"])
+
+
+def test_increments_hand_worked(eng):
+    # the hand-worked excess-of-loss fixture: YELT and its aggregate
+    # increments, e.g. (0, 0, 400) for trial (a, b, c) but (200, 200, 0) for
+    # (c, b, a) -- the same year loss, a different per-occurrence split
+    from conftest import golden
+    w = golden("w1_terms.json")
+    for case in w["cases"]:
+        _, lay = _w1_layer_gpu(eng, case["override"])
+        yh = eng.load_yet(np.array([case["trial"]], dtype=np.int32), w["catalog_size"])
+        desc = eng.load_layer(lay, w["catalog_size"])
+        for mode in (P.MODE_MEAN, P.MODE_PLAIN):
+            y = np.empty(1, dtype=np.float32)
+            ye = np.empty(3, dtype=np.float32)
+            P.ara_run_layer_yelt(eng.ctx, yh, desc, mode, 1, 0, 1, y, ye)
+            inc = P.ara_yelt_increments(eng.ctx, yh, 0, 1, lay.agg_retention, lay.agg_limit, ye)
+            assert y[0] == case["Y"] and list(ye) == case["yelt"]
+            assert list(inc) == case["increments"], (case, list(inc))
+        P.ara_free_yet(eng.ctx, yh)
+
+
+@pytest.mark.parametrize("fixed", [True, False])
+def test_increments_vs_oracle(eng, fixed):
+    torch = torch_cuda()
+    if fixed:
+        wl = synth.tiny()
+        lay = wl.layers[0]
+        C, N = wl.catalog_size, wl.n_trials
+        ev = wl.yet()
+        yh = eng.load_yet(ev, C)
+        offs = np.arange(N + 1, dtype=np.int64) * wl.events_per_trial
+    else:
+        rng = np.random.default_rng(41)
+        N, C = 150, 400
+        lens = rng.integers(0, 200, N)
+        lens[[0, 3, 149]] = 0
+        lens[10] = 130                                          # more than two chunks of 64
+        offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        ev = rng.integers(0, C, offs[-1], dtype=np.int32)
+        wl = synth.custom(N, 1, C, 6, 60, 160, seed=42)
+        lay = wl.layers[0]
+        yh = eng.load_yet(ev, C, trial_offsets=offs)
+    desc = eng.load_layer(lay, C)
+    t0, t1 = (0, N) if fixed else (2, 140)
+    n_occ = int(offs[t1] - offs[t0])
+    y, om, ye = run_yelt(eng, yh, desc, P.MODE_PLAIN, 5, t0, t1, n_occ)
+    inc_dev = P.ara_yelt_increments(eng.ctx, yh, t0, t1, lay.agg_retention, lay.agg_limit,
+                                    torch.from_numpy(ye.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    inc = inc_dev.cpu().numpy().astype(np.float64)
+    inc_host = P.ara_yelt_increments(eng.ctx, yh, t0, t1, lay.agg_retention, lay.agg_limit, ye.astype(np.float32))
+    assert np.array_equal(inc_host.astype(np.float64), inc)       # host and device buffers agree
+    for i in range(t0, t1):
+        lo, hi = int(offs[i] - offs[t0]), int(offs[i + 1] - offs[t0])
+        if hi == lo:
+            continue
+        row = ev[offs[i]:offs[i + 1]].reshape(1, -1) if not fixed else ev[i:i + 1]
+        yo, g, _, yeo = oracle.run_layer(lay, row, [i], C, 5, yelt=True)
+        inco = oracle.yelt_increments(yeo, lay.agg_retention, lay.agg_limit)[0]
+        # each running sum moves by at most the trial's YELT error, each A_k too
+        tol = 2 * (REL_TOL * g[0] + ABS_TOL) + 1e-6 * abs(yo[0])
+        assert np.all(np.abs(inc[lo:hi] - inco) <= tol), f"trial {i}"
+        # the increments telescope to the year loss
+        assert abs(inc[lo:hi].sum() - y[i - t0]) <= 1e-6 * max(1.0, y[i - t0]) + 1e-3
+    # increments are order-dependent: with the trial's events reversed the
+    # year loss stays (within rounding) but the split moves
+    if fixed:
+        assert np.any(inc != 0)
+
+
+def test_increments_errors(eng):
+    wl = synth.custom(8, 4, 50, 1, 5, 10, seed=3)
+    yh = eng.load_yet(wl.yet(), 50)
+    ye = np.zeros(32, dtype=np.float32)
+    with pytest.raises(P.AraError) as e:
+        P.ara_yelt_increments(eng.ctx, yh, 0, 9, 0.0, 1.0, ye)
+    assert e.value.status == P.ARA_E_RANGE
+    with pytest.raises(P.AraError) as e:
+        P.ara_yelt_increments(eng.ctx, yh, 0, 8, -1.0, 1.0, ye)
+    assert e.value.status == P.ARA_E_INVAL
