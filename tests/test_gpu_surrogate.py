@@ -23,6 +23,8 @@ pytestmark = pytest.mark.gpu
 PML_TVAR_REL = 1e-3
 DRAW_TOL = 1e-3
 RPS = (10.0, 50.0, 100.0, 250.0)
+# the training recipe of the paper-scale runs (about 3 s on the GPU)
+TRAIN_TUPLES, TRAIN_EPOCHS, CALIB_POINTS = 10_000_000, 20, 4_000_000
 
 
 @pytest.fixture(scope="module")
@@ -39,8 +41,8 @@ def trained():
     imports this state, so no test depends on another having run first."""
     torch_cuda()
     with P.Engine(0) as e:
-        losses = P.ara_surrogate_train(e.ctx, 1_048_576, epochs=4, batch=4096, lr=3e-3, seed=11)
-        cmax, cbias, marked = P.ara_surrogate_calibrate(e.ctx, 2_000_000, seed=12, tol=DRAW_TOL)
+        losses = P.ara_surrogate_train(e.ctx, TRAIN_TUPLES, epochs=TRAIN_EPOCHS, batch=4096, lr=3e-3, seed=11)
+        cmax, cbias, marked = P.ara_surrogate_calibrate(e.ctx, CALIB_POINTS, seed=12, tol=DRAW_TOL)
         state = P.ara_surrogate_export(e.ctx)
     return {"losses": losses, "cmax": cmax, "cbias": cbias, "marked": marked, "state": state}
 
@@ -128,7 +130,7 @@ def test_train_calibrate_and_error_bounds(eng, trained, tmp_path):
     _, used2 = P.ara_surrogate_eval(eng.ctx, np.array([0.1, 60.0]), np.array([1.0, 2.0]), np.array([0.3, 0.3]))
     assert list(used2) == [0, 0]
     # the region table is a deterministic function of the weights and the held-out seed
-    cmax2, cbias2, marked2 = P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=DRAW_TOL)
+    cmax2, cbias2, marked2 = P.ara_surrogate_calibrate(eng.ctx, CALIB_POINTS, seed=12, tol=DRAW_TOL)
     assert np.array_equal(cmax2, cmax) and np.array_equal(cbias2, cbias) and marked2 == marked
     # checkpoint round trip reproduces the same answers
     path = str(tmp_path / "sur.npz")
