@@ -249,6 +249,26 @@ ara_status ara_risk_measures(ara_ctx *ctx, const float *ylt, int64_t n_trials,
                              double *pml_out, double *tvar_out, void *hip_stream);
 
 /*
+ * The same PML and TVaR, for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): this
+ * call allocates nothing and does not synchronise.  ylt: device, n_trials
+ * floats (n_trials < 2^32); return_periods: host, n_rp doubles, read before
+ * the call returns; out: device, 2*n_rp doubles written asynchronously on
+ * hip_stream (NULL = the null stream) as out[2r] = PML, out[2r+1] = TVaR of
+ * return period r.  The kernels are those of ara_risk_measures, so the
+ * results are identical.  Their scratch (64 KiB: histograms, select state,
+ * per-block sums) is a static device array, one per GPU, held until the
+ * process ends and addressed from ara_create.  Limits: n_rp <= 16
+ * (ARA_E_INVAL beyond that, the scratch's size); host ylt or out is
+ * ARA_E_INVAL.  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (several streams or contexts at once) race and must be
+ * ordered by the caller.
+ */
+ara_status ara_risk_measures_noalloc(ara_ctx *ctx, const float *ylt, int64_t n_trials,
+                                     const double *return_periods, int32_t n_rp,
+                                     double *out, void *hip_stream);
+
+/*
  * Auxiliary device calls (the building blocks of ara_run_layer, exposed for
  * per-draw checks and for labelling training data of the sampling surrogate).
  *

@@ -72,6 +72,7 @@ def lib() -> C.CDLL:
             "ara_run_layer_yelt": (i32, [vp, i32, C.POINTER(LayerDesc), C.c_int, u32, i64, i64, vp, vp, vp, vp]),
             "ara_run_layers": (i32, [vp, i32, C.POINTER(LayerDesc), i32, C.c_int, u32, C.POINTER(vp), vp]),
             "ara_risk_measures": (i32, [vp, vp, i64, vp, i32, vp, vp, vp]),
+            "ara_risk_measures_noalloc": (i32, [vp, vp, i64, vp, i32, vp, vp]),
             "ara_sum_ylts": (i32, [vp, C.POINTER(vp), i32, i64, vp, vp]),
             "ara_normal_quantile": (i32, [vp, vp, i64, vp]),
             "ara_philox_uniforms": (i32, [vp, vp, i64, u32, u32, vp, vp]),
@@ -337,6 +338,16 @@ def ara_risk_measures(ctx, ylt, return_periods: Iterable[float] = DEFAULT_RETURN
     _check(ctx, lib().ara_risk_measures(ctx, _ptr(ylt), n, rps.ctypes.data, rps.shape[0], pml.ctypes.data,
                                         tvar.ctypes.data, _stream(stream, ylt)))
     return pml, tvar
+
+
+def ara_risk_measures_noalloc(ctx, ylt, out, return_periods: Iterable[float] = DEFAULT_RETURN_PERIODS,
+                              n_trials=None, stream=None):
+    """PML/TVaR into the device tensor ``out`` (2 * len(return_periods) doubles:
+    PML, TVaR per return period) with no allocation and no synchronisation."""
+    rps = np.ascontiguousarray(list(return_periods), dtype=np.float64)
+    n = int(n_trials if n_trials is not None else ylt.numel())
+    _check(ctx, lib().ara_risk_measures_noalloc(ctx, _ptr(ylt), n, rps.ctypes.data, rps.shape[0], _ptr(out),
+                                                _stream(stream, ylt, out)))
 
 
 def ara_set_profiling(ctx, enabled: bool) -> None:

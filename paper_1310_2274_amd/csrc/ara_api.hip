@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -104,7 +105,23 @@ struct ara_ctx {
     // pool cap needs it, or on ara_destroy.
     std::vector<DevBuf> pool;
     uint64_t pooled = 0;
+    // device address of this GPU's copy of the allocation-free scratch array
+    void* scratch_dev = nullptr;
 };
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free risk measures (ara_risk_measures_noalloc):
+// radix histograms, select state and per-block tail sums.  Each GPU the
+// library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in):
+// ara_create looks up each device's address once, with that device current,
+// and kernels receive that address.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = 64 * 1024;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxScratchDevices];
 
 namespace {
 
@@ -689,6 +706,20 @@ ara_status ara_create(int device, uint64_t hbm_budget_bytes, ara_ctx** out)
         ara_destroy(c);
         return ARA_E_DEVICE;
     }
+    if (device < kMaxScratchDevices) {
+        // once per device, with that device current (set above)
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[device]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                (void)hipGetLastError();
+                ara_destroy(c);
+                return ARA_E_DEVICE;
+            }
+            g_scratch_dev[device] = p;
+        }
+        c->scratch_dev = g_scratch_dev[device];
+    }
     *out = c;
     return ARA_OK;
 }
@@ -1203,6 +1234,7 @@ ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const doub
     if (!c) return ARA_E_STATE;
     if (!ylt || !rps || !pml || !tvar || n_rp < 1 || n_rp > kMaxRp || n < 1)
         return fail(c, ARA_E_INVAL, "bad arguments to ara_risk_measures");
+    if (n > (int64_t)UINT32_MAX) return fail(c, ARA_E_RANGE, "n_trials above 2^32 - 1");
     uint32_t ks[kMaxRp];
     for (int r = 0; r < n_rp; ++r) {
         if (!(rps[r] > 0.0) || !is_finite(rps[r])) return fail(c, ARA_E_INVAL, "return period must be positive");
@@ -1244,6 +1276,47 @@ ara_status ara_risk_measures(ara_ctx* c, const float* ylt, int64_t n, const doub
     }
     return ARA_OK;
 }
+
+ara_status ara_risk_measures_noalloc(ara_ctx* c, const float* ylt, int64_t n, const double* rps, int32_t n_rp,
+                                     double* out, void* hip_stream)
+{
+    if (!c) return ARA_E_STATE;
+    if (c->poisoned) return fail(c, ARA_E_STATE, "context is unusable after a device error");
+    if (!ylt || !rps || !out || n < 1 || n_rp < 1)
+        return fail(c, ARA_E_INVAL, "bad arguments to ara_risk_measures_noalloc");
+    if (n_rp > kMaxRp)
+        return fail(c, ARA_E_INVAL, "ara_risk_measures_noalloc: %d return periods, at most %d fit its scratch",
+                    n_rp, kMaxRp);
+    if (n > (int64_t)UINT32_MAX) return fail(c, ARA_E_RANGE, "n_trials above 2^32 - 1");
+    if (!c->scratch_dev)
+        return fail(c, ARA_E_STATE, "ara_risk_measures_noalloc: no scratch on device %d", c->device);
+    uint32_t ks[kMaxRp];
+    for (int r = 0; r < n_rp; ++r) {
+        if (!(rps[r] > 0.0) || !is_finite(rps[r])) return fail(c, ARA_E_INVAL, "return period must be positive");
+        const double k = std::floor((double)n / rps[r]);
+        if (k < 1.0) return fail(c, ARA_E_RANGE, "floor(N/RP) < 1 for RP %g", rps[r]);
+        ks[r] = (uint32_t)k;
+    }
+    if (!is_device_ptr(ylt) || !is_device_ptr(out))
+        return fail(c, ARA_E_INVAL, "ara_risk_measures_noalloc takes device ylt and out");
+    HIPCHK(c, hipSetDevice(c->device));
+    char* q = (char*)c->scratch_dev;
+    SelectWs ws;
+    ws.hist = (uint32_t*)q;
+    q += align256(kMaxRp * 256 * 4);
+    ws.state = (uint32_t*)q;
+    q += align256(2 * kMaxRp * 4);
+    ws.partial = (double*)q;
+    q += align256(kSelectBlocks * kMaxRp * 8);
+    ws.out = out;
+    // k_rm_init clears the histograms and the select state, so nothing a
+    // previous call left in the scratch is read
+    HIPCHK(c, launch_risk_measures(ylt, n, ks, n_rp, ws, (hipStream_t)hip_stream));
+    return ARA_OK;
+}
+static_assert(((kMaxRp * 256 * 4 + 255) / 256 * 256) + ((2 * kMaxRp * 4 + 255) / 256 * 256) +
+                      ((kSelectBlocks * kMaxRp * 8 + 255) / 256 * 256) <= kScratchBytes,
+              "risk-measure scratch exceeds the static array");
 
 ara_status ara_set_profiling(ara_ctx* c, int32_t enabled)
 {
