@@ -10,16 +10,22 @@ resident in HBM before timing starts.
 
 Printed: one JSON line with the metric (trial-events/s of the plain form),
 the roofline of the dominant kernel, the streaming-phase (mean mode)
-roofline, the surrogate form (speed and PML/TVaR difference), optional
-portfolio-batch and serving legs, and the FP64 oracle timed on this host on
-a bounded sample of the same workload.
+roofline, the PML/TVaR error of each sampling form against the FP64
+oracle's measures of the same workload (tests/golden/, written by a script
+that runs only the oracle), the surrogate and table forms, the 64-layer
+portfolio batch and the serving loop (plain and surrogate), and the FP64
+oracle timed on this host on fixed slices of the same YET (all cores and one
+core).
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -29,56 +35,94 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0                 # MI355X HBM3E
-# VALU issue peak in lane-instructions/s: MI355X's FP32 vector rate of
-# 157.3 TFLOP/s counts an FMA as two flops, i.e. 78.6e12 FP32 lane-instructions
-# per second (256 CUs x 128 lanes x 2.4 GHz).  SQ_INSTS_VALU x 64 counts every
-# VALU instruction once, so FP64 and transcendental instructions, which issue
-# at lower rates, make the achieved figure an underestimate, never an overcount.
-PEAK_VALU_TOPS = 157.3 / 2
-# VALU lane-instructions per draw of the plain layer kernel on this workload,
-# SQ_INSTS_VALU x 64 / draws from rocprofv3 (profiles/k_layer_plain_*_counters.md).
-VALU_OPS_PER_DRAW = 746.2
-# Bytes per launch of the plain layer kernel at 800,000 trials between L2 and
-# the memory fabric: FETCH_SIZE (x2, copy-kernel calibration) + WRITE_SIZE,
-# measured on the 100,000-trial slice and scaled by 8.
-TRAFFIC_BYTES = 8 * (2.0 * 25379206.7 + 1.0 * 344259.3) * 1024
-# The same for one 800,000-trial mean-mode pass (k_mean_slice + k_mean_finish,
-# profiles/k_mean_slice_paper800k_trace.md).
-MEAN_TRAFFIC_BYTES = (2.0 * (1669229.0 + 28132.0) + 1.0 * (56297.0 + 3125.0)) * 1024
+# VALU issue ceiling in lane-instructions/s: each SIMD issues one wave64 VALU
+# instruction every 4 cycles (16 lanes per cycle), so 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.32e12.  The FP32 vector peak of 157.3 TFLOP/s is this
+# rate x 2 (an FMA counts two flops) x 2 (packed FP32, not used here).
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_800k_oracle.json")
+PROFILE_PLAIN = os.path.join(ROOT, "profiles", "k_layer_plain_paper800k_counters.md")
+PROFILE_MEAN = os.path.join(ROOT, "profiles", "k_mean_slice_paper800k_trace.md")
+# the sources that define the layer and mean kernels: counters taken on other
+# sources do not describe the kernels this run times
+KERNEL_SOURCES = ("ara_kernels.hip", "ara_math.hpp", "ara_wave.hpp", "ara_internal.hpp")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def count_draws(yet, layer, catalog_size) -> int:
-    """Number of (trial, slot, XELT) hits: the draws one pass makes."""
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1310_2274_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profile_constants(path: str) -> dict:
+    """`key: value` lines of a profile summary's constants block, and whether
+    they were taken on the current kernel sources."""
+    if not os.path.exists(path):
+        return {"current": False}
+    text = open(path).read()
+    m = re.search(r"<!-- bench constants(.*?)-->", text, re.S)
+    vals = {}
+    for line in (m.group(1).splitlines() if m else []):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    vals["current"] = vals.get("sources_sha256") == kernel_sources_sha256()
+    return vals
+
+
+def event_counts(yet, catalog_size) -> np.ndarray:
+    """Occurrences of each event in the YET (each is one draw per XELT holding it)."""
     cnt = np.zeros(catalog_size, dtype=np.int64)
-    for e in layer.elts:
-        cnt[e.event_id] += 1
-    total = 0
     for lo in range(0, yet.shape[0], 65536):
-        total += int(cnt[yet[lo:lo + 65536]].sum())
-    return total
+        cnt += np.bincount(yet[lo:lo + 65536].ravel(), minlength=catalog_size)
+    return cnt
 
 
-def cpu_baseline(wl, seconds: float, threads: int):
+def count_draws(occ, layer) -> int:
+    """Number of (trial, slot, XELT) hits: the draws one pass makes."""
+    return int(sum(int(occ[e.event_id].sum()) for e in layer.elts))
+
+
+def cpu_baseline(wl, seconds_all: float, seconds_one: float):
+    """The FP64 oracle (C, OpenMP over trials) on fixed leading slices of the
+    YET: trials 0..7,999 on every core this process may use, and a slice sized
+    to about `seconds_one` on one core (the sequential run), each extrapolated
+    linearly to all trials (trials are independent)."""
     import oracle
     if not os.path.exists(oracle.LIB):
         oracle.build()
     lay = wl.layers[0]
-    done, t_used, chunk = 0, 0.0, 256
-    while t_used < seconds and done < wl.n_trials:
-        trials = np.arange(done, min(done + chunk, wl.n_trials))
-        rows = wl.yet_rows(trials)
-        t0 = time.perf_counter()
-        oracle.run_layer(lay, rows, trials, wl.catalog_size, wl.seed, threads=threads)
-        t_used += time.perf_counter() - t0
-        done += trials.size
-    return {"value": done * wl.events_per_trial / t_used, "unit": "trial-events/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"trials 0..{done - 1} of the {wl.n_trials}-trial YET ({done * wl.events_per_trial} "
-                      f"trial-events, {t_used:.1f} s, FP64 C oracle, OpenMP over trials)"}
+    K, N = wl.events_per_trial, wl.n_trials
+
+    def run(n_trials, threads, budget):
+        done, t_used, chunk = 0, 0.0, 250
+        while done < n_trials and t_used < budget:
+            trials = np.arange(done, min(done + chunk, n_trials))
+            rows = wl.yet_rows(trials)
+            t0 = time.perf_counter()
+            oracle.run_layer(lay, rows, trials, wl.catalog_size, wl.seed, threads=threads)
+            t_used += time.perf_counter() - t0
+            done += trials.size
+        return done, t_used
+
+    cores = len(os.sched_getaffinity(0))
+    n_all, t_all = run(min(8000, N), cores, 4 * seconds_all)
+    rate = n_all * K / t_all
+    n_one, t_one = run(min(8000, N), 1, seconds_one)
+    rate1 = n_one * K / t_one
+    return {"value": rate, "unit": "trial-events/s", "cores": cores, "kind": "oracle",
+            "sample": f"trials 0..{n_all - 1} of the {N}-trial YET ({n_all * K} trial-events) in {t_all:.1f} s, "
+                      f"FP64 C oracle, OpenMP over trials on {cores} threads",
+            "extrapolated_full_pass_s": N * K / rate,
+            "single_core": {"value": rate1, "unit": "trial-events/s", "cores": 1,
+                            "sample": f"trials 0..{n_one - 1} ({n_one * K} trial-events) in {t_one:.1f} s",
+                            "extrapolated_full_pass_s": N * K / rate1}}
 
 
 def autotune(P, eng, yh, desc, mode, n_trials):
@@ -94,6 +138,8 @@ def autotune(P, eng, yh, desc, mode, n_trials):
 
 
 def timed_steps(P, torch, eng, yh, desc, mode, seed, out, rps, steps, warmup):
+    """Wall time per step (run + risk measures), mean layer-kernel time, time of
+    the run alone, and the last step's PML/TVaR."""
     for _ in range(warmup):
         P.ara_run_layer(eng.ctx, yh, desc, mode, seed, out)
         P.ara_risk_measures(eng.ctx, out, rps)
@@ -108,30 +154,74 @@ def timed_steps(P, torch, eng, yh, desc, mode, seed, out, rps, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     P.ara_set_profiling(eng.ctx, False)
-    return dt / steps, float(np.mean(kms)), pml, tvar
+    # the run alone (no risk measures), back to back
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        P.ara_run_layer(eng.ctx, yh, desc, mode, seed, out)
+    torch.cuda.synchronize()
+    dt_run = time.perf_counter() - t1
+    return dt / steps, float(np.mean(kms)), dt_run / steps, pml, tvar
+
+
+def oracle_errors(wl, pml, tvar):
+    """Relative PML/TVaR errors against the FP64 oracle's measures of the same
+    workload over all its trials (tests/golden/), when they are there."""
+    if not os.path.exists(GOLDEN):
+        return None
+    g = json.load(open(GOLDEN))
+    if g.get("workload") != wl.name or g.get("n_trials") != wl.n_trials or g.get("seed") != wl.seed:
+        return None
+    po, to = np.array(g["pml"]), np.array(g["tvar"])
+    return {"pml_rel_err_vs_oracle": (np.abs(pml - po) / po).tolist(),
+            "tvar_rel_err_vs_oracle": (np.abs(tvar - to) / to).tolist(),
+            "oracle_pml": g["pml"], "oracle_tvar": g["tvar"],
+            "oracle": "tests/golden/paper_800k_oracle.json (FP64 oracle over every trial)"}
+
+
+def surrogate_share(P, eng, handles, layer, occ, n=1_000_000, seed=5):
+    """Share of the pass's draws the network answers (the rest fall back to the
+    exact inverse): draws sampled in proportion to their entries' occurrence
+    counts, u uniform on the 2^-24 grid, answered by ara_surrogate_eval."""
+    rng = np.random.default_rng(seed)
+    a_all, b_all, w_all = [], [], []
+    for h, e in zip(handles, layer.elts):
+        a, b = P.ara_elt_params(eng.ctx, h, e.n)
+        a_all.append(a)
+        b_all.append(b)
+        w_all.append(occ[e.event_id].astype(np.float64))
+    a, b, w = np.concatenate(a_all), np.concatenate(b_all), np.concatenate(w_all)
+    pick = rng.choice(a.size, size=n, p=w / w.sum())
+    u = (2 * rng.integers(0, 2 ** 23, n) + 1) * 2.0 ** -24
+    ok = a[pick] > 0                                   # degenerate entries take no quantile
+    _, used = P.ara_surrogate_eval(eng.ctx, a[pick][ok], b[pick][ok], u[ok])
+    return float(used.sum()) / n
 
 
 def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s, plain_pml, plain_tvar,
-                  n_tuples, epochs, ckpt):
+                  n_tuples, epochs, ckpt, occ):
     t0 = time.perf_counter()
     losses = P.ara_surrogate_train(eng.ctx, n_tuples, epochs=epochs, batch=4096, lr=3e-3, seed=11)
+    torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 4_000_000, seed=12, tol=1e-3)
     log(f"surrogate trained in {t_train:.1f} s (loss {losses[0]:.2e} -> {losses[-1]:.2e}), "
         f"{marked}/{P.SUR_CELLS} cells fall back")
     if ckpt:
         P.save_surrogate(eng.ctx, ckpt)
+    share = surrogate_share(P, eng, list(desc._keep), wl.layers[0], occ)
     tile = autotune(P, eng, yh, desc, P.MODE_SURROGATE, min(wl.n_trials, 100_000))["waves_per_workgroup"]
-    step_s, kms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_SURROGATE, wl.seed, out, rps, steps, warmup)
+    step_s, kms, run_s, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_SURROGATE, wl.seed, out, rps,
+                                                steps, warmup)
     rel_p = np.abs(pml - plain_pml) / np.abs(plain_pml)
     rel_t = np.abs(tvar - plain_tvar) / np.abs(plain_tvar)
-    return {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
-            "speedup_vs_plain": plain_step_s / step_s, "pml": pml.tolist(), "tvar": tvar.tolist(),
-            "pml_rel_diff_vs_plain": rel_p.tolist(), "tvar_rel_diff_vs_plain": rel_t.tolist(),
-            "train": {"tuples": n_tuples, "epochs": epochs, "seconds": t_train, "final_mse": float(losses[-1])},
-            "fallback_cells": int(marked), "cells": P.SUR_CELLS, "waves_per_workgroup": tile,
-            "note": "PML/TVaR differences are against the plain GPU path, which matches the FP64 oracle per "
-                    "trial far inside 1e-5 of the gross loss (tests/test_gpu_parity.py)"}
+    res = {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
+           "speedup_vs_plain": plain_step_s / step_s, "pml": pml.tolist(), "tvar": tvar.tolist(),
+           "pml_rel_diff_vs_plain": rel_p.tolist(), "tvar_rel_diff_vs_plain": rel_t.tolist(),
+           "train": {"tuples": n_tuples, "epochs": epochs, "seconds": t_train, "final_mse": float(losses[-1])},
+           "fallback_cells": int(marked), "cells": P.SUR_CELLS, "share_of_draws_answered_by_network": share,
+           "waves_per_workgroup": tile}
+    res.update(oracle_errors(wl, pml, tvar) or {})
+    return res
 
 
 def table_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s, plain_pml, plain_tvar):
@@ -141,27 +231,30 @@ def table_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s
     P.ara_run_layer(eng.ctx, yh, desc, P.MODE_TABLE, wl.seed, out)      # builds the XELTs' tables once
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
-    step_s, kms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_TABLE, wl.seed, out, rps, steps, warmup)
+    step_s, kms, _, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_TABLE, wl.seed, out, rps, steps, warmup)
     rel_p = np.abs(pml - plain_pml) / np.abs(plain_pml)
     rel_t = np.abs(tvar - plain_tvar) / np.abs(plain_tvar)
-    return {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
-            "speedup_vs_plain": plain_step_s / step_s, "pml_rel_diff_vs_plain": rel_p.tolist(),
-            "tvar_rel_diff_vs_plain": rel_t.tolist(), "first_run_with_table_build_s": t_build,
-            "note": "per-draw error against the FP64 inverse below 2e-4 relative and 2e-5 of max_l "
-                    "(tests/test_gpu_table.py)"}
+    res = {"trial_events_per_s": wl.trial_events / step_s, "ms_per_step": step_s * 1e3, "kernel_ms": kms,
+           "speedup_vs_plain": plain_step_s / step_s, "pml_rel_diff_vs_plain": rel_p.tolist(),
+           "tvar_rel_diff_vs_plain": rel_t.tolist(), "first_run_with_table_build_s": t_build}
+    res.update(oracle_errors(wl, pml, tvar) or {})
+    return res
 
 
-def portfolio_leg(P, torch, synth, steps):
+def portfolio_leg(P, torch, synth, steps, sur_state):
+    """64 layers over one 200,000-trial YET in one launch per step, plain and
+    surrogate (the surrogate trained on the paper workload, imported)."""
     wl = synth.portfolio()
     eng = P.Engine(0)
     yh = eng.load_yet(wl.yet(), wl.catalog_size)
     descs = [eng.load_layer(l, wl.catalog_size) for l in wl.layers]
     outs = [torch.empty(wl.n_trials, device="cuda") for _ in descs]
     res = {"waves_per_workgroup": autotune(P, eng, yh, descs[0], P.MODE_PLAIN, 50_000)["waves_per_workgroup"]}
-    for name, mode in (("plain", P.MODE_PLAIN), ("surrogate", P.MODE_SURROGATE)):
+    modes = [("plain", P.MODE_PLAIN)] + ([("surrogate", P.MODE_SURROGATE)] if sur_state is not None else [])
+    for name, mode in modes:
         if mode == P.MODE_SURROGATE:
-            P.ara_surrogate_train(eng.ctx, 4_000_000, epochs=10, batch=4096, lr=3e-3, seed=11)
-            P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
+            s = sur_state
+            P.ara_surrogate_import(eng.ctx, s["params"], s["adam_m"], s["adam_v"], s["step"], s["mask"], s["bias"])
         P.ara_run_layers(eng.ctx, yh, descs, mode, wl.seed, outs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -172,6 +265,8 @@ def portfolio_leg(P, torch, synth, steps):
         res[name] = {"ms_per_step": dt * 1e3,
                      "trial_events_per_s": len(descs) * wl.trial_events / dt}
         log(f"portfolio {name}: {dt * 1e3:.1f} ms for {len(descs)} layers")
+    if "surrogate" in res:
+        res["surrogate"]["speedup_vs_plain"] = res["plain"]["ms_per_step"] / res["surrogate"]["ms_per_step"]
     eng.close()
     res["workload"] = f"{wl.n_trials} trials x {wl.events_per_trial} events, {len(wl.layers)} layers " \
                       f"({sum(len(l.elts) for l in wl.layers)} XELTs), one launch per step"
@@ -221,33 +316,43 @@ def correlated_leg(P, torch, synth, steps):
     return res
 
 
-def serving_leg(P, torch, synth, rate, n_warm, n_meas, mode_name):
+def serving_leg(P, torch, synth, runs, sur_state):
+    """The serving loop on a resident 1,000,000-trial YET: a Poisson stream of
+    pricing requests per (mode, rate, warm-up, measured) run; p50/p99 latency
+    from arrival to PML/TVaR and the sustained trial-event rate."""
     from paper_1310_2274_amd import serving
     wl = synth.serving_yet()
     eng = P.Engine(0)
     yh = eng.load_yet(wl.yet(), wl.catalog_size)
-    mode = P.MODE_SURROGATE if mode_name == "surrogate" else P.MODE_PLAIN
-    if mode == P.MODE_SURROGATE:
-        P.ara_surrogate_train(eng.ctx, 4_000_000, epochs=10, batch=4096, lr=3e-3, seed=11)
-        P.ara_surrogate_calibrate(eng.ctx, 2_000_000, seed=12, tol=1e-3)
-    n = n_warm + n_meas
-    arr = serving.poisson_arrivals(rate, n, seed=4)
-    reqs = [serving.Request(i, synth.pricing_request(i), seed=1000 + i, arrival=float(arr[i])) for i in range(n)]
-    srv = serving.PricingServer(eng, yh, wl.n_trials, wl.events_per_trial, wl.catalog_size, mode,
-                                hbm_budget_bytes=64 << 30, tile=65536)
-    t0 = time.perf_counter()
-    done = srv.run_open_loop(reqs)
-    wall = time.perf_counter() - t0
-    meas = [r for r in done if r.req_id >= n_warm]
-    st = serving.latency_stats(meas)
+    out = []
+    for mode_name, rate, n_warm, n_meas in runs:
+        mode = P.MODE_SURROGATE if mode_name == "surrogate" else P.MODE_PLAIN
+        if mode == P.MODE_SURROGATE:
+            if sur_state is None:
+                continue
+            s = sur_state
+            P.ara_surrogate_import(eng.ctx, s["params"], s["adam_m"], s["adam_v"], s["step"], s["mask"], s["bias"])
+        n = n_warm + n_meas
+        arr = serving.poisson_arrivals(rate, n, seed=4)
+        reqs = [serving.Request(i, synth.pricing_request(i), seed=1000 + i, arrival=float(arr[i])) for i in range(n)]
+        srv = serving.PricingServer(eng, yh, wl.n_trials, wl.events_per_trial, wl.catalog_size, mode,
+                                    hbm_budget_bytes=64 << 30, tile=65536)
+        t0 = time.perf_counter()
+        done = srv.run_open_loop(reqs)
+        wall = time.perf_counter() - t0
+        meas = [r for r in done if r.req_id >= n_warm]
+        st = serving.latency_stats(meas)
+        st.update({"rate_req_per_s": rate, "mode": mode_name, "requests": n_meas, "warmup_requests": n_warm,
+                   "completed_req_per_s": len(done) / wall,
+                   "trial_events_per_s": len(done) * wl.trial_events / wall, "wall_s": wall, "ticks": srv.ticks,
+                   "budget_refusals": srv.refusals, "hbm_budget_bytes": 64 << 30})
+        log(f"serving {mode_name} @ {rate}/s: p50 {st['p50_s'] * 1e3:.0f} ms, p99 {st['p99_s'] * 1e3:.0f} ms, "
+            f"{st['completed_req_per_s']:.1f} req/s completed")
+        out.append(st)
     eng.close()
-    st.update({"rate_req_per_s": rate, "mode": mode_name, "requests": n_meas, "warmup_requests": n_warm,
-               "trial_events_per_s": len(done) * wl.trial_events / wall, "wall_s": wall, "ticks": srv.ticks,
-               "budget_refusals": srv.refusals,
-               "workload": f"resident YET {wl.n_trials} x {wl.events_per_trial}, catalog {wl.catalog_size}; "
-                           f"requests of log-uniform 1-32 XELTs x 10k-60k entries"})
-    log(f"serving {mode_name} @ {rate}/s: p50 {st['p50_s'] * 1e3:.0f} ms, p99 {st['p99_s'] * 1e3:.0f} ms")
-    return st
+    return {"runs": out,
+            "workload": f"resident YET {wl.n_trials} x {wl.events_per_trial}, catalog {wl.catalog_size}; Poisson "
+                        f"requests of log-uniform 1-32 XELTs x 10k-60k entries, 64 GiB admission budget"}
 
 
 def copy_probe():
@@ -264,6 +369,18 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
 
 
+def parse_serve(spec: str, default_meas: int, default_warm: int):
+    """'plain:20,surrogate:20:100' -> [(mode, rate, warm-up, measured)]."""
+    runs = []
+    for item in [s for s in spec.split(",") if s]:
+        parts = item.split(":")
+        mode, rate = parts[0], float(parts[1])
+        meas = int(parts[2]) if len(parts) > 2 else default_meas
+        warm = int(parts[3]) if len(parts) > 3 else default_warm
+        runs.append((mode, rate, warm, meas))
+    return runs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,15 +393,16 @@ def main():
     ap.add_argument("--sur-tuples", type=int, default=10_000_000)
     ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--sur-ckpt", default="")
-    ap.add_argument("--portfolio", action="store_true", help="add the 64-layer portfolio-batch leg")
-    ap.add_argument("--correlated", action="store_true",
-                    help="add the correlated multi-program portfolio leg (sigma_C > 0, program totals)")
-    ap.add_argument("--serve", default="", help="serving leg: comma-separated request rates, e.g. 5,20")
-    ap.add_argument("--serve-mode", default="plain", choices=["plain", "surrogate"])
-    ap.add_argument("--serve-requests", type=int, default=600)
-    ap.add_argument("--serve-warmup", type=int, default=60)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="CPU baseline budget (0 = skip)")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default trial tile (1 wavefront per workgroup for the plain mode, 4 for the surrogate)")
+    ap.add_argument("--no-portfolio", action="store_true", help="skip the 64-layer portfolio-batch leg")
+    ap.add_argument("--no-correlated", action="store_true",
+                    help="skip the correlated multi-program portfolio leg (sigma_C > 0, program totals)")
+    ap.add_argument("--serve", default="plain:20:300:30,surrogate:20:100:20,surrogate:5:60:10",
+                    help="serving runs, comma-separated mode:rate[:measured[:warm-up]] ('' = none)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU baseline: about this many seconds per slice, all cores and one core (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default trial tile (1 wavefront per workgroup for the plain mode, 4 for the "
+                         "surrogate)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (FETCH_SIZE/WRITE_SIZE calibration under rocprofv3)")
     args = ap.parse_args()
@@ -310,7 +428,8 @@ def main():
     N, K = wl.n_trials, wl.events_per_trial
     log(f"generating {N}x{K} YET")
     yet = wl.yet()
-    draws = count_draws(yet, lay, wl.catalog_size)
+    occ = event_counts(yet, wl.catalog_size)
+    draws = count_draws(occ, lay)
     eng = P.Engine(0)
     yh = eng.load_yet(yet, wl.catalog_size)
     desc = eng.load_layer(lay, wl.catalog_size)
@@ -325,33 +444,64 @@ def main():
         tune["plain"] = autotune(P, eng, yh, desc, P.MODE_PLAIN, N)
         log(f"trial tile (plain): {tune['plain']['waves_per_workgroup']} waves/workgroup, "
             f"slice ms {tune['plain']['slice_ms']}")
-    step_s, kernel_ms, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps,
-                                               args.steps, args.warmup)
+    step_s, kernel_ms, run_s, pml, tvar = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps,
+                                                      args.steps, args.warmup)
     value = N * K / step_s
     log(f"plain: {step_s * 1e3:.2f} ms/step, layer kernel {kernel_ms:.2f} ms")
+    plain_vs_oracle = oracle_errors(wl, pml, tvar)
+    if plain_vs_oracle:
+        log(f"plain PML/TVaR vs FP64 oracle: max rel err "
+            f"{max(plain_vs_oracle['pml_rel_err_vs_oracle'] + plain_vs_oracle['tvar_rel_err_vs_oracle']):.2e}")
     # occurrence exceedance beside the aggregate: PML/TVaR of the largest occurrence loss per trial (untimed)
     om = torch.empty(N, dtype=torch.float32, device="cuda")
     P.ara_run_layer_ex(eng.ctx, yh, desc, P.MODE_PLAIN, wl.seed, 0, N, out, om)
     oep_pml, oep_tvar = P.ara_risk_measures(eng.ctx, om, rps)
     del om
-    ach = VALU_OPS_PER_DRAW * draws / (kernel_ms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s", "frac": ach / PEAK_VALU_TOPS,
-            "traffic": TRAFFIC_BYTES if N == 800_000 else None, "kernel": "k_layer_plain", "kernel_ms": kernel_ms,
-            "draws_per_launch": draws, "draws_per_s": draws / (kernel_ms * 1e-3),
-            "ops_per_draw": VALU_OPS_PER_DRAW}
+
+    pc = profile_constants(PROFILE_PLAIN)
+    opd = float(pc["valu_lane_instructions_per_draw"]) if "valu_lane_instructions_per_draw" in pc else None
+    ach = opd * draws / (kernel_ms * 1e-3) / 1e12 if opd else None
+    traffic = None
+    if pc["current"] and N == 800_000 and "fetch_kib_per_launch" in pc:
+        traffic = (float(pc["fetch_scale"]) * float(pc["fetch_kib_per_launch"]) +
+                   float(pc["write_scale"]) * float(pc["write_kib_per_launch"])) * 1024
+    roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+            "frac": ach / PEAK_VALU_TOPS if ach else None, "traffic": traffic,
+            "kernel": "k_layer_plain", "kernel_ms": kernel_ms, "draws_per_launch": draws,
+            "draws_per_s": draws / (kernel_ms * 1e-3), "ops_per_draw": opd,
+            "ops_unit": "VALU lane-instructions (SQ_INSTS_VALU x 64 / draws)",
+            "counters_match_kernel_sources": pc["current"],
+            "valu_busy": float(pc["valu_busy"]) if "valu_busy" in pc else None,
+            "note": "peak = one wave64 VALU instruction per SIMD per 4 cycles; part of the stream issues on "
+                    "the second VALU pipe (SQ_ACTIVE_INST_VALU2), so the counted rate can exceed it"}
 
     mean_leg = None
     if not args.no_mean_leg:
+        before = P.lib().ara_bytes_in_use(eng.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.ara_run_layer(eng.ctx, yh, desc, P.MODE_MEAN, wl.seed, out)     # builds the slice-major YET copy
+        torch.cuda.synchronize()
+        first_s = time.perf_counter() - t0
+        copy_bytes = P.lib().ara_bytes_in_use(eng.ctx) - before
         if not args.no_autotune:
             tune["mean"] = autotune(P, eng, yh, desc, P.MODE_MEAN, min(N, 200_000))
-        mstep, mk, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_MEAN, wl.seed, out, rps, max(3, args.steps), 2)
+        mstep, mk, _, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_MEAN, wl.seed, out, rps,
+                                         max(3, args.steps), 2)
         gbs = (N * K * 4 + N * 4) / (mk * 1e-3) / 1e9
+        mc = profile_constants(PROFILE_MEAN)
+        mtraffic = None
+        if mc["current"] and N == 800_000 and "fetch_kib_per_launch" in mc:
+            mtraffic = (float(mc["fetch_scale"]) * float(mc["fetch_kib_per_launch"]) +
+                        float(mc["write_scale"]) * float(mc["write_kib_per_launch"])) * 1024
         mean_leg = {"bound": "hbm", "kernel": "k_mean_slice + k_mean_finish", "kernel_ms": mk, "achieved": gbs,
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
                     "algorithmic_bytes": N * K * 4 + N * 4, "ms_per_step": mstep * 1e3,
-                    "trial_events_per_s": N * K / mstep,
-                    "traffic": MEAN_TRAFFIC_BYTES if N == 800_000 else None}
-        log(f"mean mode: kernel {mk:.3f} ms = {gbs:.0f} GB/s")
+                    "trial_events_per_s": N * K / mstep, "traffic": mtraffic,
+                    "counters_match_kernel_sources": mc["current"],
+                    "first_run_with_slice_copy_s": first_s, "slice_copy_device_bytes": int(copy_bytes)}
+        log(f"mean mode: kernel {mk:.3f} ms = {gbs:.0f} GB/s (first run with the slice-major copy "
+            f"{first_s * 1e3:.0f} ms, {copy_bytes / 1e9:.2f} GB)")
 
     tab = None
     if not args.no_table:
@@ -360,26 +510,30 @@ def main():
             f"max PML/TVaR rel diff {max(tab['pml_rel_diff_vs_plain'] + tab['tvar_rel_diff_vs_plain']):.2e} "
             f"(first run with the table build {tab['first_run_with_table_build_s']:.2f} s)")
 
-    sur = None
+    sur, sur_state = None, None
     if not args.no_surrogate:
         sur = surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar,
-                            args.sur_tuples, args.sur_epochs, args.sur_ckpt)
+                            args.sur_tuples, args.sur_epochs, args.sur_ckpt, occ)
+        sur_state = P.ara_surrogate_export(eng.ctx)
+        err = sur.get("pml_rel_err_vs_oracle")
         log(f"surrogate: {sur['ms_per_step']:.2f} ms/step, x{sur['speedup_vs_plain']:.2f} vs plain, "
-            f"max PML/TVaR rel diff {max(sur['pml_rel_diff_vs_plain'] + sur['tvar_rel_diff_vs_plain']):.2e}")
+            f"{sur['share_of_draws_answered_by_network']:.3f} of draws answered by the network, "
+            f"max PML/TVaR rel diff vs plain {max(sur['pml_rel_diff_vs_plain'] + sur['tvar_rel_diff_vs_plain']):.2e}"
+            + (f", vs oracle {max(err + sur['tvar_rel_err_vs_oracle']):.2e}" if err else ""))
     eng.close()
+    del yet
 
-    port = portfolio_leg(P, torch, synth, max(1, args.steps // 2)) if args.portfolio else None
-    corr = correlated_leg(P, torch, synth, max(1, args.steps // 2)) if args.correlated else None
+    port = None if args.no_portfolio else portfolio_leg(P, torch, synth, max(1, args.steps // 2), sur_state)
+    corr = None if args.no_correlated else correlated_leg(P, torch, synth, max(1, args.steps // 2))
     serve = None
-    if args.serve:
-        serve = [serving_leg(P, torch, synth, float(r), args.serve_warmup, args.serve_requests, args.serve_mode)
-                 for r in args.serve.split(",")]
+    runs = parse_serve(args.serve, 300, 30)
+    if runs:
+        serve = serving_leg(P, torch, synth, runs, sur_state)
 
     cpu = None
     if args.cpu_seconds > 0:
-        threads = len(os.sched_getaffinity(0))
-        log(f"CPU oracle baseline on {threads} threads")
-        cpu = cpu_baseline(wl, args.cpu_seconds, threads)
+        log(f"CPU oracle baseline on {len(os.sched_getaffinity(0))} threads and on one")
+        cpu = cpu_baseline(wl, args.cpu_seconds, args.cpu_seconds)
 
     rec = {
         "metric": "trial-events/s", "value": value, "unit": "trial-events/s", "n_gpus": 1,
@@ -388,9 +542,12 @@ def main():
         "config": {"workload": f"{N} trials x {K} events/trial, 100,000-event catalog, 1 layer of 16 XELTs "
                                f"(20k-50k entries), plain inverse-Beta sampling, PML/TVaR at 10/50/100/250 yr",
                    "n_trials": N, "events_per_trial": K, "n_elts": len(lay.elts), "draws_per_step": draws},
+        "run_only": {"ms": run_s * 1e3, "trial_events_per_s": N * K / run_s, "draws_per_s": draws / run_s,
+                     "note": "ara_run_layer alone, without ara_risk_measures"},
         "roofline": roof,
         "roofline_streaming": mean_leg,
         "trial_tile": tune or None,
+        "plain_vs_oracle": plain_vs_oracle,
         "table_mode": tab,
         "surrogate": sur,
         "portfolio": port,
