@@ -20,7 +20,6 @@ core).
 from __future__ import annotations
 
 import argparse
-import glob
 import hashlib
 import json
 import math
@@ -198,14 +197,21 @@ def surrogate_share(P, eng, handles, layer, occ, n=1_000_000, seed=5):
 
 
 def surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s, plain_pml, plain_tvar,
-                  n_tuples, epochs, ckpt, occ):
-    t0 = time.perf_counter()
-    losses = P.ara_surrogate_train(eng.ctx, n_tuples, epochs=epochs, batch=4096, lr=3e-3, seed=11)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 4_000_000, seed=12, tol=1e-3)
-    log(f"surrogate trained in {t_train:.1f} s (loss {losses[0]:.2e} -> {losses[-1]:.2e}), "
-        f"{marked}/{P.SUR_CELLS} cells fall back")
+                  n_tuples, epochs, ckpt, occ, load=""):
+    if load:
+        # a checkpoint of an earlier run (for profiling the layer kernel without thousands of training launches)
+        P.load_surrogate(eng.ctx, load)
+        marked = int(P.ara_surrogate_export(eng.ctx)["mask"].sum())
+        losses, t_train = np.array([math.nan]), math.nan
+        log(f"surrogate loaded from {load}, {marked}/{P.SUR_CELLS} cells fall back")
+    else:
+        t0 = time.perf_counter()
+        losses = P.ara_surrogate_train(eng.ctx, n_tuples, epochs=epochs, batch=4096, lr=3e-3, seed=11)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        cmax, cbias, marked = P.ara_surrogate_calibrate(eng.ctx, 4_000_000, seed=12, tol=1e-3)
+        log(f"surrogate trained in {t_train:.1f} s (loss {losses[0]:.2e} -> {losses[-1]:.2e}), "
+            f"{marked}/{P.SUR_CELLS} cells fall back")
     if ckpt:
         P.save_surrogate(eng.ctx, ckpt)
     share = surrogate_share(P, eng, list(desc._keep), wl.layers[0], occ)
@@ -392,7 +398,8 @@ def main():
     ap.add_argument("--no-table", action="store_true", help="skip the table-mode leg")
     ap.add_argument("--sur-tuples", type=int, default=10_000_000)
     ap.add_argument("--sur-epochs", type=int, default=20)
-    ap.add_argument("--sur-ckpt", default="")
+    ap.add_argument("--sur-ckpt", default="", help="save the trained surrogate here (.npz)")
+    ap.add_argument("--sur-load", default="", help="load the surrogate from this checkpoint instead of training")
     ap.add_argument("--no-portfolio", action="store_true", help="skip the 64-layer portfolio-batch leg")
     ap.add_argument("--no-correlated", action="store_true",
                     help="skip the correlated multi-program portfolio leg (sigma_C > 0, program totals)")
@@ -513,7 +520,7 @@ def main():
     sur, sur_state = None, None
     if not args.no_surrogate:
         sur = surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar,
-                            args.sur_tuples, args.sur_epochs, args.sur_ckpt, occ)
+                            args.sur_tuples, args.sur_epochs, args.sur_ckpt, occ, args.sur_load)
         sur_state = P.ara_surrogate_export(eng.ctx)
         err = sur.get("pml_rel_err_vs_oracle")
         log(f"surrogate: {sur['ms_per_step']:.2f} ms/step, x{sur['speedup_vs_plain']:.2f} vs plain, "
