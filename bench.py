@@ -247,6 +247,65 @@ def table_leg(P, torch, eng, yh, desc, wl, out, rps, steps, warmup, plain_step_s
     return res
 
 
+def layout_leg(P, torch, synth, eng, yh, desc, wl, out, rps, steps, plain_kernel_ms, plain_ylt):
+    """The hashed layer table against the direct one: on the paper workload
+    (the layer holds 99.6% of the catalog's events) and on a 20M-event catalog
+    that the layer covers sparsely (about 5%)."""
+    res = {}
+    P.ara_set_table_kind(eng.ctx, P.TABLE_HASHED)
+    try:
+        _, kms, _, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out, rps, steps, 1)
+        same = bool(torch.equal(out, plain_ylt))
+    finally:
+        P.ara_set_table_kind(eng.ctx, P.TABLE_DIRECT)
+    res["paper"] = {"direct_kernel_ms": plain_kernel_ms, "hashed_kernel_ms": kms, "ylt_identical": same}
+    log(f"layer table on the paper workload: direct {plain_kernel_ms:.2f} ms, hashed {kms:.2f} ms, "
+        f"identical YLT {same}")
+    sw = synth.sparse_catalog()
+    e2 = P.Engine(0)
+    try:
+        yh2 = e2.load_yet(sw.yet(), sw.catalog_size)
+        d2 = e2.load_layer(sw.layers[0], sw.catalog_size)
+        o2 = torch.empty(sw.n_trials, device="cuda")
+        ylts, row = {}, {}
+        for name, kind in (("direct", P.TABLE_DIRECT), ("hashed", P.TABLE_HASHED)):
+            P.ara_set_table_kind(e2.ctx, kind)
+            _, kms, run_s, _, _ = timed_steps(P, torch, e2, yh2, d2, P.MODE_PLAIN, sw.seed, o2, rps, steps, 1)
+            ylts[name] = o2.clone()
+            row[f"{name}_kernel_ms"] = kms
+            row[f"{name}_trial_events_per_s"] = sw.trial_events / run_s
+        row["ylt_identical"] = bool(torch.equal(ylts["direct"], ylts["hashed"]))
+        row["workload"] = (f"{sw.n_trials} trials x {sw.events_per_trial} events over a {sw.catalog_size}-event "
+                           f"catalog, 16 XELTs of 20k-60k entries ({sum(e.n for e in sw.layers[0].elts)} in all)")
+        res["sparse_catalog"] = row
+        log(f"layer table on the sparse 20M catalog: direct {row['direct_kernel_ms']:.2f} ms, "
+            f"hashed {row['hashed_kernel_ms']:.2f} ms, identical YLT {row['ylt_identical']}")
+    finally:
+        e2.close()
+    return res
+
+
+def variable_leg(P, torch, synth, steps, fixed_trial_events_per_s):
+    """The paper layer over 800,000 trials of U{800..1,500} events (CSR)."""
+    wl, ev, offs = synth.paper_variable()
+    eng = P.Engine(0)
+    try:
+        yh = eng.load_yet(ev, wl.catalog_size, trial_offsets=offs)
+        desc = eng.load_layer(wl.layers[0], wl.catalog_size)
+        out = torch.empty(wl.n_trials, device="cuda")
+        _, kms, run_s, _, _ = timed_steps(P, torch, eng, yh, desc, P.MODE_PLAIN, wl.seed, out,
+                                          P.DEFAULT_RETURN_PERIODS, steps, 1)
+    finally:
+        eng.close()
+    te = int(offs[-1])
+    res = {"workload": f"{wl.n_trials} trials of U{{800..1500}} events ({te} trial-events, CSR), the paper layer",
+           "kernel_ms": kms, "ms_per_run": run_s * 1e3, "trial_events_per_s": te / run_s,
+           "vs_fixed_length_trial_events_per_s": (te / run_s) / fixed_trial_events_per_s}
+    log(f"variable-length trials: {kms:.2f} ms kernel, {te / run_s:.3e} trial-events/s "
+        f"({res['vs_fixed_length_trial_events_per_s']:.3f} of the fixed-length rate)")
+    return res
+
+
 def portfolio_leg(P, torch, synth, steps, sur_state):
     """64 layers over one 200,000-trial YET in one launch per step, plain and
     surrogate (the surrogate trained on the paper workload, imported)."""
@@ -401,6 +460,8 @@ def main():
     ap.add_argument("--sur-ckpt", default="", help="save the trained surrogate here (.npz)")
     ap.add_argument("--sur-load", default="", help="load the surrogate from this checkpoint instead of training")
     ap.add_argument("--no-portfolio", action="store_true", help="skip the 64-layer portfolio-batch leg")
+    ap.add_argument("--no-layouts", action="store_true", help="skip the hashed-against-direct layer-table leg")
+    ap.add_argument("--no-variable", action="store_true", help="skip the variable-length (CSR) trials leg")
     ap.add_argument("--no-correlated", action="store_true",
                     help="skip the correlated multi-program portfolio leg (sigma_C > 0, program totals)")
     ap.add_argument("--serve", default="plain:20:300:30,surrogate:20:100:20,surrogate:5:60:10",
@@ -517,6 +578,14 @@ def main():
             f"max PML/TVaR rel diff {max(tab['pml_rel_diff_vs_plain'] + tab['tvar_rel_diff_vs_plain']):.2e} "
             f"(first run with the table build {tab['first_run_with_table_build_s']:.2f} s)")
 
+    layouts = None
+    if not args.no_layouts:
+        plain_ylt = out.clone()
+        P.ara_run_layer(eng.ctx, yh, desc, P.MODE_PLAIN, wl.seed, plain_ylt)
+        layouts = layout_leg(P, torch, synth, eng, yh, desc, wl, out, rps, max(2, args.steps // 2), kernel_ms,
+                             plain_ylt)
+        del plain_ylt
+
     sur, sur_state = None, None
     if not args.no_surrogate:
         sur = surrogate_leg(P, torch, eng, yh, desc, wl, out, rps, args.steps, args.warmup, step_s, pml, tvar,
@@ -530,6 +599,7 @@ def main():
     eng.close()
     del yet
 
+    var = None if args.no_variable else variable_leg(P, torch, synth, max(2, args.steps // 2), N * K / run_s)
     port = None if args.no_portfolio else portfolio_leg(P, torch, synth, max(1, args.steps // 2), sur_state)
     corr = None if args.no_correlated else correlated_leg(P, torch, synth, max(1, args.steps // 2))
     serve = None
@@ -556,6 +626,8 @@ def main():
         "trial_tile": tune or None,
         "plain_vs_oracle": plain_vs_oracle,
         "table_mode": tab,
+        "layer_table_layouts": layouts,
+        "variable_length_trials": var,
         "surrogate": sur,
         "portfolio": port,
         "correlated_portfolio": corr,

@@ -222,6 +222,23 @@ ara_status ara_run_prepared(ara_ctx *ctx, int32_t yet_handle, const int32_t *lay
  * ignores the tile.
  */
 ara_status ara_set_trial_tile(ara_ctx *ctx, ara_mode mode, int32_t wpb);
+
+/*
+ * Layout of the per-layer event table the kernels look events up in
+ * (section 4.1 weighs direct-access tables against compact ones for the
+ * lookup step of Algorithm 1).  ARA_TABLE_DIRECT (the default): one 16-byte
+ * row per catalog event, read with one access.  ARA_TABLE_HASHED: rows only for
+ * the events some XELT of the layer holds, in a table of 2^b slots (b the
+ * smallest with 2^b >= 2 x min(catalog, entries); 32 bytes a slot, the event
+ * id beside its row), found by a multiplicative hash and linear probing; it is smaller than the direct table
+ * when the layer's XELTs cover a small share of a large catalog.  Applies to
+ * the tables of runs and of layers prepared after the call (plain, table and
+ * surrogate modes; the mean mode keeps its per-event table).  Results do not
+ * depend on the layout.  ARA_E_INVAL for another value.
+ */
+#define ARA_TABLE_DIRECT 0
+#define ARA_TABLE_HASHED 1
+ara_status ara_set_table_kind(ara_ctx *ctx, int32_t kind);
 ara_status ara_autotune(ara_ctx *ctx, int32_t yet_handle, const int32_t *layer_handles, int32_t n_layers,
                         int64_t n_trials, int32_t *best_wpb_out, float *ms_out);
 

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(PKG, "libara.so")
 
 ARA_OK, ARA_E_INVAL, ARA_E_RANGE, ARA_E_NOMEM, ARA_E_BUDGET, ARA_E_DEVICE, ARA_E_STATE = 0, -1, -2, -3, -4, -5, -6
 MODE_MEAN, MODE_PLAIN, MODE_SURROGATE, MODE_TABLE = 0, 1, 2, 3
+TABLE_DIRECT, TABLE_HASHED = 0, 1
 STATUS_NAMES = {0: "ARA_OK", -1: "ARA_E_INVAL", -2: "ARA_E_RANGE", -3: "ARA_E_NOMEM", -4: "ARA_E_BUDGET",
                 -5: "ARA_E_DEVICE", -6: "ARA_E_STATE"}
 DEFAULT_RETURN_PERIODS = (10.0, 50.0, 100.0, 250.0)
@@ -79,6 +80,7 @@ def lib() -> C.CDLL:
             "ara_set_profiling": (i32, [vp, i32]),
             "ara_prepare_layer": (i32, [vp, C.POINTER(LayerDesc), C.c_int, C.POINTER(i32)]),
             "ara_set_trial_tile": (i32, [vp, C.c_int, i32]),
+            "ara_set_table_kind": (i32, [vp, i32]),
             "ara_autotune": (i32, [vp, i32, C.POINTER(i32), i32, i64, C.POINTER(i32), vp]),
             "ara_free_layer": (i32, [vp, i32]),
             "ara_run_prepared": (i32, [vp, i32, C.POINTER(i32), i32, C.POINTER(u32), i64, i64, C.POINTER(vp),
@@ -348,6 +350,11 @@ def ara_risk_measures_noalloc(ctx, ylt, out, return_periods: Iterable[float] = D
     n = int(n_trials if n_trials is not None else ylt.numel())
     _check(ctx, lib().ara_risk_measures_noalloc(ctx, _ptr(ylt), n, rps.ctypes.data, rps.shape[0], _ptr(out),
                                                 _stream(stream, ylt, out)))
+
+
+def ara_set_table_kind(ctx, kind: int) -> None:
+    """Layer-table layout for later runs and prepared layers (TABLE_DIRECT or TABLE_HASHED)."""
+    _check(ctx, lib().ara_set_table_kind(ctx, int(kind)))
 
 
 def ara_set_profiling(ctx, enabled: bool) -> None:

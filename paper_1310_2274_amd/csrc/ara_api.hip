@@ -107,6 +107,7 @@ struct ara_ctx {
     uint64_t pooled = 0;
     // device address of this GPU's copy of the allocation-free scratch array
     void* scratch_dev = nullptr;
+    int32_t table_kind = ARA_TABLE_DIRECT;   // layer tables built from now on
 };
 
 // ---------------------------------------------------------------------------
@@ -361,12 +362,26 @@ void plan_layer(const ara_layer_desc* L, const std::vector<const EltRec*>& es, L
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// log2 of the hashed layer table's slot count: at least twice the events the
+// layer can hold (at most min(C, entries)), so probes stay short.
+uint32_t hash_bits(int32_t C, const LayerPlan& p)
+{
+    const uint64_t keys = std::min<uint64_t>((uint64_t)C, (uint64_t)p.total);
+    uint32_t b = 6;
+    while ((1ull << b) < 2 * keys) ++b;
+    return b;
+}
+
 // Workspace bytes for one layer's tables.
-size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
+size_t table_bytes(int mode, int32_t C, const LayerPlan& p, int32_t kind)
 {
     if (mode == ARA_MODE_MEAN) return align256((size_t)C * 4);
     size_t b = align256((size_t)C * 16) + 2 * align256((size_t)C * 4) + align256(scan_scratch_words(C) * 4) +
                align256(p.total * sizeof(EntryRec));
+    if (kind == ARA_TABLE_HASHED) {
+        const size_t slots = (size_t)1 << hash_bits(C, p);
+        b += align256(slots * 32);
+    }
     if (p.has_corr) b += align256(p.total * 8);
     if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
     if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
@@ -376,7 +391,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p)
 
 // Build one layer's tables inside ws at `base`; fills p.dev table pointers.
 ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* base, const EltDev* elts_dev,
-                        hipStream_t s)
+                        hipStream_t s, int32_t kind)
 {
     const int32_t J = p.dev.J;
     if (mode == ARA_MODE_MEAN) {
@@ -415,6 +430,7 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     }
     HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, ptab, s));
     p.dev.rows = rows;
+    p.dev.hbits = 0;
     p.dev.pent = pent;
     p.dev.pcw = pcw;
     p.dev.psol = psol;
@@ -424,6 +440,16 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         q += align256(p.total * sizeof(SurEntry));
         HIPCHK(c, launch_sur_entries(pent, (int64_t)p.total, psur, s));
         p.dev.psur = psur;
+    }
+    if (kind == ARA_TABLE_HASHED) {
+        // the kernels read the compact table; the direct rows it was built from stay unread
+        const uint32_t bits = hash_bits(C, p);
+        const size_t slots = (size_t)1 << bits;
+        uint4* hs = (uint4*)q;
+        q += align256(slots * 32);
+        HIPCHK(c, launch_layer_hash(C, rows, hs, bits, s));
+        p.dev.rows = hs;
+        p.dev.hbits = bits;
     }
     return ARA_OK;
 }
@@ -513,7 +539,7 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
         if ((st = check_layer(c, y, &layers[l], es))) return st;
         if ((st = ensure_tabs(c, mode, es, s))) return st;
         plan_layer(&layers[l], es, plans[l]);
-        tab_total += table_bytes(mode, y.C, plans[l]);
+        tab_total += table_bytes(mode, y.C, plans[l], c->table_kind);
         has_corr |= plans[l].has_corr;
         maxJ = std::max(maxJ, plans[l].dev.J);
     }
@@ -557,8 +583,8 @@ ara_status run_impl(ara_ctx* c, int32_t yh, const ara_layer_desc* layers, int32_
     std::vector<LayerDev> devs((size_t)n_layers);
     for (int32_t l = 0; l < n_layers; ++l) {
         LayerPlan& p = plans[l];
-        if ((st = build_tables(c, mode, y.C, p, tb, (const EltDev*)elts_dev + first[l], s))) return st;
-        tb += table_bytes(mode, y.C, p);
+        if ((st = build_tables(c, mode, y.C, p, tb, (const EltDev*)elts_dev + first[l], s, c->table_kind))) return st;
+        tb += table_bytes(mode, y.C, p, c->table_kind);
         if (host_out[l]) {
             p.dev.ylt = (float*)ob;
             ob += align256((size_t)n * 4);
@@ -1074,7 +1100,7 @@ ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode m
     PreparedRec pr;
     LayerPlan plan;
     plan_layer(layer, es, plan);
-    const size_t bytes = table_bytes(mode, pseudo.C, plan);
+    const size_t bytes = table_bytes(mode, pseudo.C, plan, c->table_kind);
     if ((st = dev_alloc(c, pr.mem, bytes))) return st;
     void* elts_dev = nullptr;
     StageSlot* sl = nullptr;
@@ -1082,7 +1108,8 @@ ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode m
         dev_free(c, pr.mem);
         return st;
     }
-    if ((st = build_tables(c, mode, pseudo.C, plan, (char*)pr.mem.p, (const EltDev*)elts_dev, nullptr))) return st;
+    if ((st = build_tables(c, mode, pseudo.C, plan, (char*)pr.mem.p, (const EltDev*)elts_dev, nullptr, c->table_kind)))
+        return st;
     if ((st = release_stage(c, sl, nullptr))) return st;
     HIPCHK(c, hipStreamSynchronize(nullptr));
     pr.live = true;
@@ -1155,6 +1182,14 @@ ara_status ara_set_trial_tile(ara_ctx* c, ara_mode mode, int32_t wpb)
     const bool ok = wpb == 1 || wpb == 2 || wpb == 4 || (wpb == 8 && mode != ARA_MODE_SURROGATE);
     if (!ok) return fail(c, ARA_E_INVAL, "trial tile %d not available for mode %d", wpb, (int)mode);
     c->wpb[mode] = wpb;
+    return ARA_OK;
+}
+
+ara_status ara_set_table_kind(ara_ctx* c, int32_t kind)
+{
+    if (!c) return ARA_E_STATE;
+    if (kind != ARA_TABLE_DIRECT && kind != ARA_TABLE_HASHED) return fail(c, ARA_E_INVAL, "unknown table kind %d", kind);
+    c->table_kind = kind;
     return ARA_OK;
 }
 

@@ -36,7 +36,10 @@ __host__ __device__ inline int row_count(uint32_t w) { return (int)(w & 127u); }
 
 // One layer of a run: its tables (built per run on the device) and terms.
 struct LayerDev {
-    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count | flags}
+    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count | flags},
+                            // or, when hbits > 0, 2^hbits hash slots of two uint4 each:
+                            // {event id (-1 empty), mask bits 0-31, mask bits 32-63, first entry}, {count | flags}
+    uint32_t hbits;         // log2 of the hashed table's slot count; 0 = direct access
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
     const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
@@ -75,6 +78,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
                              EntryRec* pent, float2* pcw, SolveRec* psol, TabRec* ptab, hipStream_t s);
 hipError_t launch_elt_tab(int32_t n, const EntryRec* ent, TabRec* tab, hipStream_t s);
+hipError_t launch_layer_hash(int32_t C, const uint4* rows, uint4* slots, uint32_t hbits, hipStream_t s);
 hipError_t launch_beta_quantile_table(const double* a, const double* b, const double* u, int64_t n, double* x,
                                       hipStream_t s);
 hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double occR, double occL,

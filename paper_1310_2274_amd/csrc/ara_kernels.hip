@@ -136,6 +136,40 @@ __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ el
 
 // Mean mode (primary uncertainty only): the loss of an event occurrence does
 // not depend on the trial, so its net-of-terms occurrence loss is tabulated.
+// Hashed layer table: the compact alternative to the direct table over the
+// catalog (section 4.1 weighs direct access against compact layouts).  Every
+// event some XELT of the layer holds gets a slot with its id and its row; the
+// slot a given event lands in may vary from build to build, the rows a lookup
+// returns do not.
+__global__ void k_hash_clear(uint4* __restrict__ slots, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        slots[2u * i] = make_uint4(0xFFFFFFFFu, 0u, 0u, 0u);
+        slots[2u * i + 1u] = make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+__global__ void k_hash_insert(int32_t C, const uint4* __restrict__ rows, uint4* __restrict__ slots, uint32_t hbits)
+{
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= C) return;
+    const uint4 r = rows[e];
+    if ((r.x | r.y) == 0u) return;
+    const uint32_t m = (1u << hbits) - 1u;
+    for (uint32_t h = layer_hash(e, hbits);; h = (h + 1u) & m) {
+        // claim the slot's key word; the rest of the slot is written by its owner alone
+        if (atomicCAS((int32_t*)&slots[2u * h].x, -1, e) == -1) {
+            uint4* S = slots + 2u * h;
+            S[0].y = r.x;
+            S[0].z = r.y;
+            S[0].w = r.z;
+            S[1] = make_uint4(r.w, 0u, 0u, 0u);
+            return;
+        }
+    }
+}
+
 __global__ void k_mean_table(int32_t C, int32_t J, const EltDev* __restrict__ elts, double occR, double occL,
                              float* __restrict__ occ_tab)
 {
@@ -331,7 +365,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 if (L.yelt) L.yelt[row + ci * kChunk + lane - L.yelt_base] = o;
                 PN[r][lane] = kFinal;
             }
-            if (__ballot(PN[r][lane] != kFinal) == 0ull) RC[r] = -1;
+            const bool settled = __ballot(PN[r][lane] != kFinal) == 0ull;
+            wave_sync();                 // every lane has read RC[r]
+            if (settled && lane == 0) RC[r] = -1;
             wave_sync();
         };
         // Evaluate the m <= 64 oldest deferred draws, one per lane, then hand
@@ -390,6 +426,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             if (!more || RC[r] >= 0)
                 while (dn > 0) flush(dn < 64 ? dn : 64, -1);
             if (!more) break;
+            wave_sync();                     // every lane has read RC[r] before lane 0 rewrites it
             PC[r][lane] = 0.0f;
             PN[r][lane] = 0;
             if (lane == 0) RC[r] = ci;
@@ -398,7 +435,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             const int32_t k = base + lane;
             const bool valid = k < len;
             uint4 rr = make_uint4(0, 0, 0, 0);
-            if (valid) rr = L.rows[y.ev[row + k]];
+            if (valid) rr = layer_row(L, y.ev[row + k]);
             if (HAS_CORR) {
                 // the event's correlated uniform and its quantile, once per slot
                 CorrEvent ce{0.0, 0.0f};
@@ -1185,6 +1222,14 @@ __global__ __launch_bounds__(256) void k_sum_ylts(const float* const* __restrict
 hipError_t launch_sum_ylts(const float* const* ylts_dev, int32_t n, int64_t nt, float* out, hipStream_t s)
 {
     if (nt > 0) hipLaunchKernelGGL(k_sum_ylts, dim3(nblocks(nt, 256)), dim3(256), 0, s, ylts_dev, n, nt, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer_hash(int32_t C, const uint4* rows, uint4* slots, uint32_t hbits, hipStream_t s)
+{
+    const uint32_t n = 1u << hbits;
+    hipLaunchKernelGGL(k_hash_clear, dim3((n + 255) / 256), dim3(256), 0, s, slots, n);
+    if (C > 0) hipLaunchKernelGGL(k_hash_insert, dim3((C + 255) / 256), dim3(256), 0, s, C, rows, slots, hbits);
     return hipGetLastError();
 }
 

@@ -447,7 +447,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
             const int32_t k = base + lane;
             const bool valid = k < len;
             uint4 r = make_uint4(0, 0, 0, 0);
-            if (valid) r = L.rows[y.ev[row + k]];
+            if (valid) r = layer_row(L, y.ev[row + k]);
             uint64_t msk = (uint64_t)r.x | ((uint64_t)r.y << 32);
             const uint32_t off = r.z;
             int remaining = row_count(r.w);

@@ -75,6 +75,28 @@ __device__ __forceinline__ void trial_range(const YetDev& y, int64_t i, int64_t&
     }
 }
 
+// The layer-table row of event e: direct access, or a probe of the hashed
+// table (multiplicative hash, linear probing; at most half the slots are
+// taken, so a probe ends at the event's slot or at an empty one).  A slot
+// keeps the key beside its row in one 32-byte line, so a probe that finds
+// the event costs one line.
+__device__ __forceinline__ uint32_t layer_hash(int32_t e, uint32_t bits)
+{
+    return ((uint32_t)e * 0x9E3779B1u) >> (32u - bits);
+}
+
+__device__ __forceinline__ uint4 layer_row(const LayerDev& L, int32_t e)
+{
+    if (L.hbits == 0u) return L.rows[e];
+    const uint32_t m = (1u << L.hbits) - 1u;
+    for (uint32_t h = layer_hash(e, L.hbits);; h = (h + 1u) & m) {
+        const uint4 a = L.rows[2u * h];
+        const uint4 b = L.rows[2u * h + 1u];
+        if ((int32_t)a.x == e) return make_uint4(a.y, a.z, a.w, b.x);
+        if ((int32_t)a.x < 0) return make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
 // Draw z for one (trial, slot, XELT) hit: section 3.1 uniforms, section 3.2
 // combination when the entry has a correlated part.
 template <bool HAS_CORR>

@@ -228,6 +228,53 @@ def correlated_portfolio(n_programs: int = 10, layers_per_program: int = 2, n_tr
     return Workload(f"correlated_{n_programs}P_{n_trials}x1000", n_trials, K, C, layers, seed=seed, yet_seed=seed)
 
 
+def variable_length_yet(N: int, kmin: int, kmax: int, C: int, seed: int = MASTER_SEED):
+    """A YET of trials with U{kmin..kmax} events each (section 2.1: ~800-1,500
+    occurrences per trial), ids uniform in [0, C), in CSR form: (event ids
+    int32 [total], trial offsets int64 [N+1]).  Drawn in blocks of YET_BLOCK
+    trials like the fixed-length YET."""
+    lens = _rng(seed, 7, N, kmin, kmax).integers(kmin, kmax + 1, size=N)
+    offs = np.zeros(N + 1, dtype=np.int64)
+    np.cumsum(lens, out=offs[1:])
+    ev = np.empty(int(offs[-1]), dtype=np.int32)
+    for b in range((N + YET_BLOCK - 1) // YET_BLOCK):
+        lo, hi = b * YET_BLOCK, min(N, (b + 1) * YET_BLOCK)
+        ev[offs[lo]:offs[hi]] = _rng(seed, 8, b).integers(0, C, size=int(offs[hi] - offs[lo]), dtype=np.int32)
+    return ev, offs
+
+
+def paper_variable(n_trials: int = 800_000, kmin: int = 800, kmax: int = 1500, seed: int = MASTER_SEED):
+    """The paper-scale layer (the same 16 ELTs as :func:`paper_scale`) over a
+    YET of variable-length trials, U{kmin..kmax} events each, in CSR form.
+    The aggregate terms are sized from the mean trial length.  Returns
+    (workload, event ids, trial offsets); the workload's events_per_trial is
+    the longest trial."""
+    base = paper_scale(n_trials, seed)
+    lay = base.layers[0]
+    kmean = 0.5 * (kmin + kmax)
+    E = kmean * sum(e.n for e in lay.elts) / base.catalog_size
+    lay.agg_retention = 1.12 * E * L0
+    lay.agg_limit = 0.17 * E * L0
+    ev, offs = variable_length_yet(n_trials, kmin, kmax, base.catalog_size, seed)
+    wl = Workload(f"paper_csr_{n_trials}x{kmin}-{kmax}_16elt", n_trials, kmax, base.catalog_size, [lay],
+                  seed=seed, yet_seed=seed)
+    return wl, ev, offs
+
+
+def sparse_catalog(n_trials: int = 200_000, C: int = 20_000_000, n_elts: int = 16, lo: int = 20_000,
+                   hi: int = 60_000, seed: int = MASTER_SEED) -> Workload:
+    """A large catalog that the layer's XELTs cover only sparsely: n_trials x
+    1,000 events over a 20,000,000-event catalog, one layer of 16 ELTs with
+    20,000-60,000 entries (about 5% of the catalog), terms as at paper scale."""
+    K = 1000
+    rng = _rng(seed, 2, 7)
+    elts = _elts(rng, C, n_elts, lo, hi)
+    E = K * sum(e.n for e in elts) / C
+    lay = Layer(elts, occ_retention=L0, occ_limit=20 * L0,
+                agg_retention=0.5 * E * L0, agg_limit=1.5 * E * L0)
+    return Workload(f"sparse_{n_trials}x1000_C{C}", n_trials, K, C, [lay], seed=seed, yet_seed=seed)
+
+
 def serving_yet(n_trials: int = 1_000_000, seed: int = MASTER_SEED) -> Workload:
     """Resident YET for ad-hoc pricing: 1,000,000 trials x 1,000 events over a
     200,000-event catalog (requests come from :func:`pricing_request`)."""
