@@ -564,7 +564,11 @@ def main():
                         float(mc["write_scale"]) * float(mc["write_kib_per_launch"])) * 1024
         mean_leg = {"bound": "hbm", "kernel": "k_mean_slice + k_mean_finish", "kernel_ms": mk, "achieved": gbs,
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "algorithmic_bytes": N * K * 4 + N * 4, "ms_per_step": mstep * 1e3,
+                    "algorithmic_bytes": N * K * 4 + N * 4,
+                    "note": "algorithmic bytes: 4 B per int32 trial-event of the YET + 4 B per trial; the kernel "
+                            "reads the slice-major copy of the YET, 2 B per trial-event (16-bit ids within a "
+                            "catalog slice), so it moves about half of them (traffic)",
+                    "ms_per_step": mstep * 1e3,
                     "trial_events_per_s": N * K / mstep, "traffic": mtraffic,
                     "counters_match_kernel_sources": mc["current"],
                     "first_run_with_slice_copy_s": first_s, "slice_copy_device_bytes": int(copy_bytes)}

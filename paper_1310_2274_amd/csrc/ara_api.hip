@@ -462,14 +462,14 @@ ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
     const int32_t ns = mean_slices(y.C);
     if (ns == 0 || y.sliced) return ARA_OK;
     y.sliced = true;
-    const uint64_t ints = (uint64_t)y.total + (uint64_t)3 * ns * (uint64_t)y.N;
+    const uint64_t ints = (uint64_t)y.total + (uint64_t)7 * ns * (uint64_t)y.N;     // ids with padding
     if (ints >= ((uint64_t)1 << 32) || y.N == 0) return ARA_OK;
     const size_t groups = (size_t)ns * (size_t)y.N;
     ara_status st;
     DevBuf scratch;
     if ((st = dev_alloc(c, y.scnt, groups * 4)) || (st = dev_alloc(c, y.soff, groups * 4)) ||
         (st = dev_alloc(c, scratch, scan_scratch_words((int64_t)groups) * 4)) ||
-        (st = dev_alloc(c, y.sev, (size_t)ints * 4 + 16))) {
+        (st = dev_alloc(c, y.sev, (size_t)ints * 2 + 16))) {
         dev_free(c, y.scnt);
         dev_free(c, y.soff);
         dev_free(c, scratch);
@@ -479,7 +479,7 @@ ara_status ensure_sliced(ara_ctx* c, YetRec& y, const YetDev& yd, hipStream_t s)
     HIPCHK(c, launch_yet_slice_count(yd, (uint32_t*)y.scnt.p, s));
     HIPCHK(c, launch_exclusive_scan((const uint32_t*)y.scnt.p, (uint32_t*)y.soff.p, (int64_t)groups,
                                     (uint32_t*)scratch.p, s));
-    HIPCHK(c, launch_yet_slice_scatter(yd, (const uint32_t*)y.soff.p, (const uint32_t*)y.scnt.p, (int32_t*)y.sev.p,
+    HIPCHK(c, launch_yet_slice_scatter(yd, (const uint32_t*)y.soff.p, (const uint32_t*)y.scnt.p, (uint16_t*)y.sev.p,
                                        s));
     dev_free(c, scratch);
     return ARA_OK;
@@ -500,7 +500,7 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
                                           (const uint32_t*)c->sur_mask.p, (const float*)c->sur_bias.p, c->wpb[mode],
                                           s));
     else if (mode == ARA_MODE_MEAN)
-        HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const int32_t*)yr.sev.p, (const uint32_t*)yr.soff.p,
+        HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const uint16_t*)yr.sev.p, (const uint32_t*)yr.soff.p,
                               (const uint32_t*)yr.scnt.p, c->ws_mean.p, yelt, s));
     else
         HIPCHK(c, launch_layers(mode, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));

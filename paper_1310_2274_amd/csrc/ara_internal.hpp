@@ -93,10 +93,10 @@ hipError_t launch_mean_table(int32_t C, int32_t J, const EltDev* elts, double oc
 int32_t mean_slices(int32_t C);
 size_t mean_workspace_bytes(int32_t C, int64_t n_trials);
 hipError_t launch_yet_slice_count(const YetDev& y, uint32_t* cnt, hipStream_t s);
-hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, int32_t* ev2,
+hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, uint16_t* ev2,
                                     hipStream_t s);
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
+                       const uint16_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
                        hipStream_t s);
 // Per-occurrence aggregate increments of trials [t0, t1): occ and inc hold
 // the trials' occurrences from row `base` of the YET on.

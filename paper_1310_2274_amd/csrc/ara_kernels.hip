@@ -566,15 +566,19 @@ constexpr int kSliceMax = 18432;             // table entries per slice (72 KB o
 constexpr int kMaxSlices = 16;
 constexpr int kMeanWaves = 16;               // wavefronts per workgroup
 constexpr int kMeanTile = 1024;              // trials per workgroup
-constexpr int kLanesPerTrial = 16;           // lanes streaming one trial's group
+constexpr int kLanesPerTrial = 8;            // lanes streaming one trial's group
 constexpr int kTrialsPerWave = 64 / kLanesPerTrial;
-constexpr int kMeanPre = 4;                 // int4 loads per lane kept in flight one batch ahead
+constexpr int kMeanPre = 3;                 // 16-byte loads per lane kept in flight one batch ahead
+constexpr int kGroupAlign = 8;              // ids per 16-byte load of the slice-major copy
+constexpr uint16_t kSlicePad = 0xFFFF;      // padding id (beyond every slice)
 
 // The slice-major copy: group (slice s, trial t) holds trial t's ids that
-// fall in slice s, in time order, padded with -1 to a multiple of four; the
-// groups of one slice are consecutive over the trials, slice after slice, so
-// a workgroup streams one contiguous run.  k_yet_count sizes the groups,
-// an exclusive scan over (slice, trial) places them, k_yet_scatter fills them.
+// fall in slice s, in time order, as 16-bit offsets into the slice (a slice
+// has at most kSliceMax < 2^16 events), padded with kSlicePad to a multiple
+// of eight (one 16-byte load); the groups of one slice are consecutive over
+// the trials, slice after slice, so a workgroup streams one contiguous run.
+// k_yet_count sizes the groups, an exclusive scan over (slice, trial) places
+// them, k_yet_scatter fills them.
 __global__ __launch_bounds__(256) void k_yet_count(YetDev y, int32_t slice_len, int32_t ns, uint32_t* __restrict__ cnt)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -589,13 +593,13 @@ __global__ __launch_bounds__(256) void k_yet_count(YetDev y, int32_t slice_len, 
             const int32_t k = k0 + lane;
             c += __popcll(__ballot(k < len && y.ev[row + k] / slice_len == sl));
         }
-        if (lane == 0) cnt[(int64_t)sl * y.N + t] = (uint32_t)((c + 3) & ~3);
+        if (lane == 0) cnt[(int64_t)sl * y.N + t] = (uint32_t)((c + kGroupAlign - 1) & ~(kGroupAlign - 1));
     }
 }
 
 __global__ __launch_bounds__(256) void k_yet_scatter(YetDev y, int32_t slice_len, int32_t ns,
                                                      const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
-                                                     int32_t* __restrict__ ev2)
+                                                     uint16_t* __restrict__ ev2)
 {
     const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (t >= y.N) return;
@@ -613,10 +617,10 @@ __global__ __launch_bounds__(256) void k_yet_scatter(YetDev y, int32_t slice_len
             const int32_t id = k < len ? y.ev[row + k] : 0;
             const bool mine = k < len && id / slice_len == sl;
             const uint64_t m = __ballot(mine);
-            if (mine) ev2[start + fill + __popcll(m & below)] = id;
+            if (mine) ev2[start + fill + __popcll(m & below)] = (uint16_t)(id - sl * slice_len);
             fill += __popcll(m);
         }
-        for (int32_t q = fill + lane; q < (int32_t)cnt[g]; q += 64) ev2[start + q] = -1;
+        for (int32_t q = fill + lane; q < (int32_t)cnt[g]; q += 64) ev2[start + q] = kSlicePad;
     }
 }
 
@@ -626,7 +630,7 @@ __global__ __launch_bounds__(256) void k_yet_scatter(YetDev y, int32_t slice_len
 // fetched while a batch is summed.
 __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_t t0, int64_t t1,
                                                                  const LayerDev* __restrict__ layers, int32_t l,
-                                                                 const int32_t* __restrict__ ev2,
+                                                                 const uint16_t* __restrict__ ev2,
                                                                  const uint32_t* __restrict__ goff,
                                                                  const uint32_t* __restrict__ gcnt, int32_t slice_len,
                                                                  int32_t ns, float2* __restrict__ part,
@@ -650,27 +654,27 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
     const int64_t nt = t1 - t0;
     const int64_t tb = tile * kMeanTile;
     const int64_t te = min(nt, tb + (int64_t)kMeanTile);
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    // where trial i's group for this slice lives: offset into the copy, length in int4
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));      // eight 16-bit ids
+    // where trial i's group for this slice lives: offset into the copy, length in 16-byte loads
     auto locate = [&](int64_t i, int64_t& at, int32_t& n4) {
         at = 0;
         n4 = 0;
         if (i < te) {
             const int64_t g = (int64_t)sl * y.N + t0 + i;
             at = goff[g];
-            n4 = (int32_t)(gcnt[g] >> 2);
+            n4 = (int32_t)(gcnt[g] / kGroupAlign);
         }
     };
     // The first kMeanPre 16-byte loads of each lane's share of a group are
     // issued one batch of trials ahead, so the next trials' ids stream in
-    // while this batch is summed; a group longer than kMeanPre * 16 int4
-    // (rare: 256 ids of one slice in one trial) reads the rest in place.
-    auto fetch = [&](int64_t at_, int32_t n4_, v4i* dst) {
-        const v4i* __restrict__ p = reinterpret_cast<const v4i*>(ev2 + at_);
+    // while this batch is summed; a group longer than kMeanPre x kLanesPerTrial
+    // loads (192 ids of one slice in one trial) reads the rest in place.
+    auto fetch = [&](int64_t at_, int32_t n4_, v4u* dst) {
+        const v4u* __restrict__ p = reinterpret_cast<const v4u*>(ev2 + at_);
 #pragma unroll
         for (int r = 0; r < kMeanPre; ++r) {
             const int32_t q = sub + r * kLanesPerTrial;
-            dst[r] = q < n4_ ? __builtin_nontemporal_load(p + q) : v4i{-1, -1, -1, -1};
+            dst[r] = q < n4_ ? __builtin_nontemporal_load(p + q) : v4u{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
         }
     };
     constexpr int64_t kStride = kTrialsPerWave * kMeanWaves;
@@ -678,37 +682,42 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
     int64_t at, at1;
     int32_t n4, n41;
     locate(first, at, n4);
-    v4i e[kMeanPre];
+    v4u e[kMeanPre];
     fetch(at, n4, e);
     locate(first + kStride, at1, n41);                   // offsets of the next batch
     for (int64_t i0 = tb + kTrialsPerWave * w; i0 < te; i0 += kStride) {
         const int64_t i = i0 + grp;
         const bool live = i < te;
-        v4i en[kMeanPre];
+        v4u en[kMeanPre];
         fetch(at1, n41, en);                             // the next batch's ids, in flight during this one
         int64_t at2;
         int32_t n42;
         locate(i + 2 * kStride, at2, n42);               // and the offsets of the batch after it
         float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, m = 0.0f;
-        auto add4 = [&](const v4i& x) {
-            const uint32_t u0 = (uint32_t)(x.x - lo), u1 = (uint32_t)(x.y - lo);
-            const uint32_t u2 = (uint32_t)(x.z - lo), u3 = (uint32_t)(x.w - lo);
-            const float v0 = u0 < un ? stab[u0] : 0.0f;          // -1 padding falls outside
+        auto add8 = [&](const v4u& x) {
+            // two ids per word; the padding id is beyond every slice
+            const uint32_t u0 = x.x & 0xFFFFu, u1 = x.x >> 16, u2 = x.y & 0xFFFFu, u3 = x.y >> 16;
+            const uint32_t u4 = x.z & 0xFFFFu, u5 = x.z >> 16, u6 = x.w & 0xFFFFu, u7 = x.w >> 16;
+            const float v0 = u0 < un ? stab[u0] : 0.0f;
             const float v1 = u1 < un ? stab[u1] : 0.0f;
             const float v2 = u2 < un ? stab[u2] : 0.0f;
             const float v3 = u3 < un ? stab[u3] : 0.0f;
-            a0 += v0;
-            a1 += v1;
-            a2 += v2;
-            a3 += v3;
-            m = fmaxf(m, fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)));
+            const float v4 = u4 < un ? stab[u4] : 0.0f;
+            const float v5 = u5 < un ? stab[u5] : 0.0f;
+            const float v6 = u6 < un ? stab[u6] : 0.0f;
+            const float v7 = u7 < un ? stab[u7] : 0.0f;
+            a0 += v0 + v4;
+            a1 += v1 + v5;
+            a2 += v2 + v6;
+            a3 += v3 + v7;
+            m = fmaxf(m, fmaxf(fmaxf(fmaxf(v0, v1), fmaxf(v2, v3)), fmaxf(fmaxf(v4, v5), fmaxf(v6, v7))));
         };
 #pragma unroll
-        for (int r = 0; r < kMeanPre; ++r) add4(e[r]);
-        const v4i* __restrict__ v4 = reinterpret_cast<const v4i*>(ev2 + at);
+        for (int r = 0; r < kMeanPre; ++r) add8(e[r]);
+        const v4u* __restrict__ v8 = reinterpret_cast<const v4u*>(ev2 + at);
 #pragma unroll 1
         for (int32_t q = sub + kMeanPre * kLanesPerTrial; q < n4; q += kLanesPerTrial)
-            add4(__builtin_nontemporal_load(v4 + q));
+            add8(__builtin_nontemporal_load(v8 + q));
 #pragma unroll
         for (int r = 0; r < kMeanPre; ++r) e[r] = en[r];
         at = at1;
@@ -728,7 +737,7 @@ __global__ __launch_bounds__(64 * kMeanWaves) void k_mean_slice(YetDev y, int64_
         }
         if (live && sub == 0) {
             part[(int64_t)sl * nt + i] = make_float2(S, Sc);
-            pmax[(int64_t)sl * nt + i] = m;
+            if (L.omax) pmax[(int64_t)sl * nt + i] = m;      // only when the largest occurrence is asked for
         }
     }
 }
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(256) void k_mean_finish(const LayerDev* __restrict_
     for (int32_t sl = 0; sl < ns; ++sl) {
         const float2 p = part[(int64_t)sl * nt + i];
         S += (double)p.x + (double)p.y;
-        m = fmaxf(m, pmax[(int64_t)sl * nt + i]);
+        if (L.omax) m = fmaxf(m, pmax[(int64_t)sl * nt + i]);
     }
     L.ylt[i] = (float)fmin(fmax(S - (double)L.aggR, 0.0), (double)L.aggL);    // aggregate terms
     if (L.omax) L.omax[i] = m;
@@ -1149,7 +1158,7 @@ hipError_t launch_yet_slice_count(const YetDev& y, uint32_t* cnt, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, int32_t* ev2,
+hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const uint32_t* cnt, uint16_t* ev2,
                                     hipStream_t s)
 {
     const int32_t ns = mean_slices(y.C);
@@ -1160,7 +1169,7 @@ hipError_t launch_yet_slice_scatter(const YetDev& y, const uint32_t* off, const 
 }
 
 hipError_t launch_mean(const YetDev& y, int64_t t0, int64_t t1, const LayerDev* layers, int32_t n_layers,
-                       const int32_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
+                       const uint16_t* ev2, const uint32_t* goff, const uint32_t* gcnt, void* ws, bool yelt,
                        hipStream_t s)
 {
     const int64_t nt = t1 - t0;
