@@ -18,6 +18,10 @@
  *   - Outputs are caller-allocated.  A device pointer (for example a torch
  *     tensor's data_ptr()) makes the call asynchronous on the given stream; a
  *     host pointer makes it synchronous.
+ *   - Every call is ordered on the device behind the context's previous call,
+ *     whatever streams they use.  Loads of XELTs and preparations of layers
+ *     return once their inputs are copied to the context's pinned staging,
+ *     without waiting for the device work they start.
  *   - hip_stream is a hipStream_t; NULL is the HIP null (default) stream,
  *     which is also torch's default stream.
  *   - One context per host thread; calls on one context must not overlap.
@@ -98,7 +102,9 @@ typedef struct {
 } ara_elt_desc;
 
 /* Load n_elts XELTs; the per-entry Beta parameters (section 3.3) are derived on
- * the device at load time.  elt_handles: out[n_elts]. */
+ * the device at load time.  elt_handles: out[n_elts].  The raw entries of all
+ * n_elts XELTs pass through one pinned host block of the context (grown to the
+ * largest call so far, kept until ara_destroy). */
 ara_status ara_load_elts(ara_ctx *ctx, int32_t catalog_size, const ara_elt_desc *elts,
                          int32_t n_elts, int32_t *elt_handles);
 ara_status ara_free_elts(ara_ctx *ctx, const int32_t *elt_handles, int32_t n);

@@ -67,6 +67,17 @@ struct StageSlot {
 constexpr size_t kStageBytes = 256 * 1024;
 constexpr int kStageSlots = 8;
 
+// Pinned host staging for bulk inputs (XELT loads): the call copies the
+// caller's arrays here and returns without waiting for the device; a slot is
+// reused once the copy out of it has completed.
+struct BulkSlot {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+constexpr int kBulkSlots = 4;
+
 }  // namespace
 
 struct ara_ctx {
@@ -87,6 +98,8 @@ struct ara_ctx {
     double* sel_host = nullptr;
     StageSlot stage[kStageSlots];
     int next_stage = 0;
+    BulkSlot bulk[kBulkSlots];
+    int next_bulk = 0;
     hipEvent_t last = nullptr;
     hipStream_t last_stream = nullptr;
     bool have_last = false;
@@ -727,6 +740,12 @@ ara_status ara_create(int device, uint64_t hbm_budget_bytes, ara_ctx** out)
             return ARA_E_DEVICE;
         }
     }
+    for (auto& bs : c->bulk) {
+        if (hipEventCreateWithFlags(&bs.done, hipEventDisableTiming) != hipSuccess) {
+            ara_destroy(c);
+            return ARA_E_DEVICE;
+        }
+    }
     if (hipHostMalloc((void**)&c->sel_host, 2 * kMaxRp * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->k_start) != hipSuccess || hipEventCreate(&c->k_stop) != hipSuccess) {
         ara_destroy(c);
@@ -788,6 +807,11 @@ void ara_destroy(ara_ctx* c)
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (auto& bs : c->bulk) {
+        if (bs.pending && bs.done) (void)hipEventSynchronize(bs.done);
+        if (bs.host) (void)hipHostFree(bs.host);
+        if (bs.done) (void)hipEventDestroy(bs.done);
     }
     if (c->sel_host) (void)hipHostFree(c->sel_host);
     if (c->k_start) (void)hipEventDestroy(c->k_start);
@@ -913,7 +937,49 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
     std::vector<uint8_t> seen((size_t)C);
     for (int j = 0; j < n_elts; ++j)
         if ((st = validate_elt(c, C, elts[j], j, seen))) return st;
+    // one pinned block and one device block hold every XELT's raw inputs:
+    // ids, mean, sigma_i, sigma_c, max (each array aligned to 256 bytes)
+    std::vector<size_t> at((size_t)n_elts + 1, 0);
+    for (int j = 0; j < n_elts; ++j) {
+        const size_t n = (size_t)elts[j].n_entries;
+        at[j + 1] = at[j] + align256(n * 4) + 4 * align256(n * 8);
+    }
+    const size_t in_bytes = at[(size_t)n_elts];
+    BulkSlot& bs = c->bulk[c->next_bulk];
+    c->next_bulk = (c->next_bulk + 1) % kBulkSlots;
+    if (bs.pending) HIPCHK(c, hipEventSynchronize(bs.done));
+    bs.pending = false;
+    if (bs.bytes < in_bytes) {
+        if (bs.host) HIPCHK(c, hipHostFree(bs.host));
+        bs.host = nullptr;
+        bs.bytes = 0;
+        const size_t want = in_bytes + in_bytes / 4;
+        if (hipHostMalloc(&bs.host, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            bs.host = nullptr;
+            return fail(c, ARA_E_NOMEM, "pinned staging of %zu bytes", want);
+        }
+        bs.bytes = want;
+    }
+    for (int j = 0; j < n_elts; ++j) {
+        const ara_elt_desc& d = elts[j];
+        const size_t n = (size_t)d.n_entries;
+        char* h = (char*)bs.host + at[j];
+        std::memcpy(h, d.event_id, n * 4);
+        h += align256(n * 4);
+        std::memcpy(h, d.mean, n * 8);
+        h += align256(n * 8);
+        std::memcpy(h, d.sigma_i, n * 8);
+        h += align256(n * 8);
+        if (d.sigma_c) std::memcpy(h, d.sigma_c, n * 8);
+        h += align256(n * 8);
+        std::memcpy(h, d.max_loss, n * 8);
+    }
     if ((st = begin_call(c, c->stream))) return st;
+    if (in_bytes && (st = ws_reserve(c, c->ws_in, in_bytes))) return st;
+    if (in_bytes) HIPCHK(c, hipMemcpyAsync(c->ws_in.p, bs.host, in_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipEventRecord(bs.done, c->stream));
+    bs.pending = true;
     for (int j = 0; j < n_elts; ++j) {
         const ara_elt_desc& d = elts[j];
         EltRec e;
@@ -936,32 +1002,27 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
             dev_free(c, e.sol);
             return st;
         }
-        // raw inputs: ids, sigma_i, sigma_c, max (the mean goes straight to its own buffer)
-        const size_t in_bytes = align256(n * 4) + 3 * align256(n * 8);
-        if ((st = ws_reserve(c, c->ws_in, in_bytes))) return st;
-        char* q = (char*)c->ws_in.p;
-        int32_t* ids = (int32_t*)q;
-        double* si = (double*)(q + align256(n * 4));
-        double* sc = (double*)(q + align256(n * 4) + align256(n * 8));
-        double* mx = (double*)(q + align256(n * 4) + 2 * align256(n * 8));
+        char* q = (char*)c->ws_in.p + at[j];
+        const int32_t* ids = (const int32_t*)q;
+        q += align256(n * 4);
+        const double* mean = (const double*)q;
+        q += align256(n * 8);
+        const double* si = (const double*)q;
+        q += align256(n * 8);
+        const double* sc = (const double*)q;
+        q += align256(n * 8);
+        const double* mx = (const double*)q;
         HIPCHK(c, hipMemsetAsync(e.idx.p, 0xFF, (size_t)C * 4, c->stream));
-        if (n) {
-            HIPCHK(c, hipMemcpyAsync(ids, d.event_id, n * 4, hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipMemcpyAsync(e.mean.p, d.mean, n * 8, hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipMemcpyAsync(si, d.sigma_i, n * 8, hipMemcpyHostToDevice, c->stream));
-            if (d.sigma_c) HIPCHK(c, hipMemcpyAsync(sc, d.sigma_c, n * 8, hipMemcpyHostToDevice, c->stream));
-            HIPCHK(c, hipMemcpyAsync(mx, d.max_loss, n * 8, hipMemcpyHostToDevice, c->stream));
-        }
+        if (n) HIPCHK(c, hipMemcpyAsync(e.mean.p, mean, n * 8, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, launch_elt_index(ids, d.n_entries, (int32_t*)e.idx.p, c->stream));
         HIPCHK(c, launch_elt_prepare(d.n_entries, (const double*)e.mean.p, si, d.sigma_c ? sc : nullptr, mx,
                                      (EntryRec*)e.ent.p, (float2*)e.cw.p, c->stream));
         HIPCHK(c, launch_elt_solve(d.n_entries, (const EntryRec*)e.ent.p, (SolveRec*)e.sol.p, c->stream));
-        // the staging buffer is reused by the next XELT: wait for this one
-        HIPCHK(c, hipStreamSynchronize(c->stream));
         e.live = true;
         c->elts.push_back(e);
         handles[j] = (int32_t)c->elts.size() - 1;
     }
+    // the device work is ordered behind this call's event; nothing waits here
     return end_call(c, c->stream);
 }
 
@@ -1111,7 +1172,7 @@ ara_status ara_prepare_layer(ara_ctx* c, const ara_layer_desc* layer, ara_mode m
     if ((st = build_tables(c, mode, pseudo.C, plan, (char*)pr.mem.p, (const EltDev*)elts_dev, nullptr, c->table_kind)))
         return st;
     if ((st = release_stage(c, sl, nullptr))) return st;
-    HIPCHK(c, hipStreamSynchronize(nullptr));
+    // no wait: runs that use the prepared layer are ordered behind this call
     pr.live = true;
     pr.mode = mode;
     pr.C = pseudo.C;

@@ -61,7 +61,8 @@ def request_bytes(layer, catalog_size: int, n_trials: int, mode: int) -> int:
 class PricingServer:
     def __init__(self, engine, yet_handle: int, n_trials: int, events_per_trial: int, catalog_size: int,
                  mode: int, hbm_budget_bytes: int, tile: int = 65536,
-                 return_periods: Sequence[float] = DEFAULT_RETURN_PERIODS, max_active: int = 128):
+                 return_periods: Sequence[float] = DEFAULT_RETURN_PERIODS, max_active: int = 128,
+                 max_inflight: int = 2):
         import torch
         self.torch = torch
         self.eng = engine
@@ -75,6 +76,8 @@ class PricingServer:
         self.tile = int(tile)
         self.rps = tuple(return_periods)
         self.max_active = int(max_active)
+        self.max_inflight = max(1, int(max_inflight))
+        self.inflight: collections.deque = collections.deque()     # one event per queued tick
         self.cursor = 0
         self.used = 0
         self.waiting: collections.deque = collections.deque()
@@ -140,8 +143,16 @@ class PricingServer:
         handles = [r.prepared for r in reqs]
         seeds = [r.seed for r in reqs]
         outs = [r.ylt.data_ptr() + 4 * t0 for r in reqs]
-        ara_run_prepared(self.ctx, self.yet, handles, seeds, t0, t1, outs,
-                         stream=self.torch.cuda.current_stream().cuda_stream)
+        stream = self.torch.cuda.current_stream()
+        ara_run_prepared(self.ctx, self.yet, handles, seeds, t0, t1, outs, stream=stream.cuda_stream)
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        self.inflight.append(ev)
+        # Bounded run-ahead: the host queues at most max_inflight ticks, so a
+        # request that arrives now starts within that many tiles instead of
+        # behind a whole wrap of queued tiles.
+        while len(self.inflight) > self.max_inflight:
+            self.inflight.popleft().synchronize()
         for r in reqs:
             r.done += t1 - t0
         self.cursor = 0 if t1 >= self.N else t1
@@ -151,6 +162,7 @@ class PricingServer:
 
     def _finish(self, r: Request) -> None:
         pml, tvar = ara_risk_measures(self.ctx, r.ylt, self.rps)    # waits for the request's last tile
+        self.inflight.clear()                                         # ... and every tick before it
         r.pml, r.tvar = pml, tvar
         r.finished_at = self.now()
         ara_free_layer(self.ctx, r.prepared)
