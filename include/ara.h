@@ -380,7 +380,7 @@ ara_status ara_normal_quantile(ara_ctx *ctx, const double *p, int64_t n, double 
 ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                              double *x_out, void *hip_stream);
 /* ara_beta_quantile_layer: the per-draw inverse exactly as the plain layer
- * kernel applies it -- the FP32 solve alone where min(a, b) >= 0.2, FP32 plus
+ * kernel applies it -- the FP32 solve alone where min(a, b) >= 0.15, FP32 plus
  * the FP64 polish below that.  Same arguments as ara_beta_quantile. */
 ara_status ara_beta_quantile_layer(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                                    double *x_out, void *hip_stream);

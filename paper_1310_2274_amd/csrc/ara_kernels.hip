@@ -351,6 +351,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
         float S = 0.0f, Sc = 0.0f, omax = 0.0f;
         int dh = 0, dn = 0;                        // deferred ring: head, count (wave-uniform)
         if (lane < kRing) RC[lane] = -1;
+        // Direct tables: each chunk's event ids are loaded one chunk ahead, so
+        // a chunk waits for one load (its rows) instead of two in a chain.
+        const bool direct = L.hbits == 0u;
+        int32_t ev_next = 0;                       // this lane's event id in the next chunk
+        if (direct && lane < len) ev_next = y.ev[row + lane];
         wave_sync();
 
         // Occurrence terms of every settled slot of ring slot r (its chunk's
@@ -435,7 +440,12 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             const int32_t k = base + lane;
             const bool valid = k < len;
             uint4 rr = make_uint4(0, 0, 0, 0);
-            if (valid) rr = layer_row(L, y.ev[row + k]);
+            if (direct) {
+                if (valid) rr = L.rows[ev_next];
+                if (k + kChunk < len) ev_next = y.ev[row + k + kChunk];
+            } else if (valid) {
+                rr = layer_row(L, y.ev[row + k]);
+            }
             if (HAS_CORR) {
                 // the event's correlated uniform and its quantile, once per slot
                 CorrEvent ce{0.0, 0.0f};

@@ -243,7 +243,7 @@ typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 // FP64 path (pol) carry tables too: they start its FP32 stage.
 struct alignas(64) SolveRec {
     float a, b;                   // alpha, beta
-    float lnB;                    // ln B(alpha, beta)
+    float lam;                    // ln B(alpha, beta) + ln min(alpha, beta), formed in FP64
     float us;                     // I_ts, as in EntryRec
     float maxl;                   // max_l
     uint32_t pol;                 // 1: the draw takes the FP64 path (needs_polish)
@@ -343,9 +343,14 @@ __host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaS
 }
 
 // Draws whose smaller shape parameter is below this take the FP64 polish; at
-// or above it the FP32 solve alone is accurate to a few 1e-6 relative (the
-// quantile's sensitivity to an error in ln I grows like 1/shape).
-constexpr double kPolishShape = 0.2;
+// or above it the FP32 solve alone, with c0 formed in FP64, is within 1e-5
+// relative of the FP64 inverse (8e-6 at worst just above the threshold, 2e-6
+// in 99 of 100 draws): the quantile's sensitivity to an error in ln I grows
+// like 1/shape, most of all near t_s, where the terms of ln I cancel.
+constexpr double kPolishShape = 0.15;
+// The same threshold for solves that start from the entry record alone (they
+// form c0 in FP32, whose error the quantile divides by the shape).
+constexpr double kPolishShapeEntry = 0.2;
 
 __host__ __device__ inline bool needs_polish(const EntryRec& E)
 {
@@ -416,7 +421,7 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
     SolveRec R;
     R.a = (float)E.a;
     R.b = (float)E.b;
-    R.lnB = (float)E.lnB;
+    R.lam = E.a == 0.0 ? 0.0f : (float)(E.lnB + log(E.a < E.b ? E.a : E.b));
     R.us = E.us;
     R.maxl = E.maxl;
     R.pol = needs_polish(E) ? 1u : 0u;
@@ -481,8 +486,9 @@ __host__ __device__ inline void beta_cf32(float t, float A, float B, float eps, 
 // From a rough start (ROUGH) the first step only has to land near the root: a
 // continued fraction good to 1e-2 suffices there, and that step never ends the
 // loop.  The loop stops once a step moves the quantile x by less than 1e-2
-// relative: cubic convergence then leaves an error of a few 1e-6 in x on the
-// shapes this path takes (min(a, b) >= kPolishShape), against the FP64 inverse.
+// relative: cubic convergence leaves far less than the FP32 evaluation noise
+// in ln I, which sets the error in x on the shapes this path takes
+// (min(a, b) >= kPolishShape): below 1e-5 against the FP64 inverse.
 constexpr float kStopX = 1e-2f;
 
 template <bool ROUGH>
@@ -546,7 +552,11 @@ __device__ inline float inv_beta32_side(bool lower, float p, const SolveRec& R)
     const float B = lower ? R.b : R.a;
     const float lnp = f32_ln(p);
     const float rA = f32_rcp(A);
-    const float c0 = -(R.lnB + f32_ln(A));
+    // c0 = -(ln B + ln A).  For a small shape the two logs cancel to O(A),
+    // and the quantile moves by the error of c0 over A, so the smaller side's
+    // c0 comes formed in FP64 (-lam); the other side adds ln(A / min(a, b)).
+    const float mn = fminf(R.a, R.b);
+    const float c0 = A == mn ? -R.lam : -(R.lam + f32_ln(A * f32_rcp(mn)));
     const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
     const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
     const float lnps = f32_ln(lower ? R.us : 1.0f - R.us);

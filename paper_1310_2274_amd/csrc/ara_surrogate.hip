@@ -486,7 +486,7 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                             QV[q] = v;
                         } else {
                             const EntryRec& E = L.pent[pi];
-                            pol = fmin(E.a, E.b) < kPolishShape;
+                            pol = fmin(E.a, E.b) < kPolishShapeEntry;
                         }
                     }
                     const uint64_t bs = __ballot(in && is_sur);

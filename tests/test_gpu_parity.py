@@ -86,18 +86,18 @@ def test_beta_quantile_paper_scale_parameters(eng):
     assert np.max(np.abs(x[visible] - xo[visible]) / xo[visible]) <= 1e-8
 
 
-@pytest.mark.parametrize("lo,hi,seed", [(1e-3, 40.0, 5), (0.2, 50.0, 6), (3e-6, 35.0, 7)])
+@pytest.mark.parametrize("lo,hi,seed", [(1e-3, 40.0, 5), (0.2, 50.0, 6), (3e-6, 35.0, 7), (0.1, 0.3, 8)])
 def test_layer_inverse_per_draw_accuracy(eng, lo, hi, seed):
     # the inverse exactly as the plain layer kernel applies it: FP32 alone
-    # where min(a, b) >= 0.2 (a few 1e-6 relative), FP32 + FP64 polish below
+    # where min(a, b) >= 0.15 (below 1e-5 relative), FP32 + FP64 polish below
     a, b, u = _grid(40000, lo, hi, seed)
     x = P.ara_beta_quantile_layer(eng.ctx, a, b, u)
     xo = oracle.beta_inc_inv_vec(u, a, b, threads=0)
     visible = xo > 1e-30
     rel = np.abs(x - xo) / np.maximum(xo, 1e-300)
-    fp32 = np.minimum(a, b) >= 0.2
+    fp32 = np.minimum(a, b) >= 0.15
     assert np.all(rel[visible & fp32] <= 1e-5), rel[visible & fp32].max()
-    assert np.quantile(rel[visible & fp32], 0.99) <= 2e-6
+    assert np.quantile(rel[visible & fp32], 0.99) <= 3e-6
     assert np.all(rel[visible & ~fp32] <= 1e-8)
     assert np.all(x[~visible] <= 1e-28)
 
@@ -116,7 +116,7 @@ def test_layer_inverse_off_grid_tails(eng, side):
     tail = 10.0 ** (-k) * rng.uniform(1.0, 9.0, n)
     big = np.exp(rng.uniform(math.log(5.0), math.log(35.0), n))
     small = np.exp(rng.uniform(math.log(0.3), math.log(3.0), n))
-    small[::4] = np.exp(rng.uniform(math.log(1e-3), math.log(0.19), n // 4))   # the FP64 path too
+    small[::4] = np.exp(rng.uniform(math.log(1e-3), math.log(0.14), n // 4))   # the FP64 path too
     if side == "upper":
         a, b, u = small, big, 1.0 - tail
     else:
@@ -124,7 +124,7 @@ def test_layer_inverse_off_grid_tails(eng, side):
     x = P.ara_beta_quantile_layer(eng.ctx, a, b, u)
     xo = oracle.beta_inc_inv_vec(u, a, b, threads=0)
     dist = np.minimum(xo, 1.0 - xo)          # distance from the nearer end of [0, 1]
-    fp32 = np.minimum(a, b) >= 0.2
+    fp32 = np.minimum(a, b) >= 0.15
     err = np.abs(x - xo)
     # FP32 solve: 1e-5 of that distance, or FP32's spacing next to 1
     assert np.all(err[fp32] <= 1e-5 * dist[fp32] + 1.2e-7), (err[fp32] / (dist[fp32] + 1e-30)).max()
