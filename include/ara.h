@@ -380,8 +380,10 @@ ara_status ara_normal_quantile(ara_ctx *ctx, const double *p, int64_t n, double 
 ara_status ara_beta_quantile(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                              double *x_out, void *hip_stream);
 /* ara_beta_quantile_layer: the per-draw inverse exactly as the plain layer
- * kernel applies it -- the FP32 solve alone where min(a, b) >= 0.15, FP32 plus
- * the FP64 polish below that.  Same arguments as ara_beta_quantile. */
+ * kernel applies it -- the continued-fraction FP32 solve where min(a, b) >=
+ * 0.2; below that the FP32 series form of the incomplete beta on the side of
+ * the small shape, with ln p, c0 and the residual's sum in FP64.  Same
+ * arguments as ara_beta_quantile. */
 ara_status ara_beta_quantile_layer(ara_ctx *ctx, const double *a, const double *b, const double *u, int64_t n,
                                    double *x_out, void *hip_stream);
 /* ara_beta_quantile_table: the per-draw inverse of the table mode (section 3.3's

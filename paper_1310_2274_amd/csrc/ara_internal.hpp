@@ -29,8 +29,8 @@ struct EltDev {
 
 // The fourth word of an event's row: the event's entry count in the layer
 // (bits 0-6) and, for its first kRowPolBits entries in rank order, whether the
-// entry takes the FP64 path (bit 7 + rank), so the solve can be chosen without
-// reading the entry.
+// entry is a small shape whose draws are deferred (bit 7 + rank), so the solve
+// can be chosen without reading the entry.
 constexpr int kRowPolBits = 25;
 __host__ __device__ inline int row_count(uint32_t w) { return (int)(w & 127u); }
 

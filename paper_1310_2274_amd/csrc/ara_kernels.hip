@@ -127,7 +127,7 @@ __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ el
         if (pcw) pcw[o] = X.cw ? X.cw[i] : make_float2(1.0f, 0.0f);
         if (psol) psol[o] = X.solve[i];
         if (ptab) ptab[o] = X.tab[i];
-        if (rank < kRowPolBits && needs_polish(E)) pol |= 1u << rank;
+        if (rank < kRowPolBits && is_small_shape(E)) pol |= 1u << rank;
         ++o;
     }
     r.w |= pol << 7;
@@ -253,13 +253,14 @@ constexpr int kChunk = 64;                   // event slots per compaction round
 constexpr int kRound = 6;                    // draws per slot per drain round (7.2 KB of LDS per wavefront)
 constexpr int kQueue = kChunk * kRound;      // queue capacity per wave
 
-// The FP64 polish of a deferred draw, out of line: a call whose registers
-// stay out of the layer kernel's allocation (inlined, they force spills in
-// the kernel's hot loops).
-__device__ __attribute__((noinline)) float polish_loss(double z, EntryRec E, const SolveRec* R)
+// The solve of a deferred draw (a small shape: the series form for its small
+// side, or a degenerate entry), out of line: a call whose registers stay out
+// of the layer kernel's allocation (inlined, they force spills in the
+// kernel's hot loops).
+__device__ __attribute__((noinline)) float deferred_loss(double z, EntryRec E, const SolveRec* R)
 {
     if (E.a == 0.0) return (float)E.lnB;       // degenerate: the mean loss
-    return E.maxl * (float)inv_beta(z, E, nullptr, R);
+    return E.maxl * inv_beta32_any(z, E, *R);
 }
 
 // The correlated draw's z (two uniforms, two FP64 normal quantiles, one
@@ -292,11 +293,12 @@ __device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot
 
 // Plain path, one wave per trial.  Each chunk of 64 event slots is drained in
 // rounds: the queued draws of a round are classified by cost.  Draws whose
-// smaller shape parameter is at least kPolishShape take the FP32 solve alone
-// and are drained 64 at a time at once.  The rest (small shapes that need the
-// FP64 polish, and degenerate entries) are few -- a handful per chunk -- so
-// they go to a per-wave deferred queue that is drained only in full waves of
-// 64 (and once, partially, at the end of the trial).  An event whose draws
+// smaller shape parameter is at least kSmallShape take the FP32 solve alone
+// and are drained 64 at a time at once.  The rest (small shapes, whose small
+// side takes the series form of the solve, and degenerate entries) are few --
+// a handful per chunk -- so they go to a per-wave deferred queue that is
+// drained only in full waves of 64 (and once, partially, at the end of the
+// trial), where the two forms do not split a solve wave.  An event whose draws
 // are still deferred keeps its partial loss in a small ring of pending chunks
 // and takes its occurrence terms once the last of them lands.  Every sum is a
 // fixed function of the trial, so the result does not depend on the launch.
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 key = meta & 0xFFFFFFu;
                 const EntryRec E = L.pent[pi];
                 const double z = HAS_CORR ? DZ[e] : draw_z<false>(tr, key, j, L.seed, L.prog, nullptr, pi);
-                const float loss = polish_loss(z, E, L.psol + pi);
+                const float loss = deferred_loss(z, E, L.psol + pi);
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
             }

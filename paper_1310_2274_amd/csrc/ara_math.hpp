@@ -239,14 +239,14 @@ constexpr float kVmapShape = 3.0f;
 typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 // One entry's record for the FP32 solve: the shapes and constants in FP32 and
-// both sides' start tables, one 64-byte line per draw.  Entries that take the
-// FP64 path (pol) carry tables too: they start its FP32 stage.
+// both sides' start tables, one 64-byte line per draw.  Small-shape entries
+// (pol) carry tables too: they start the series form of the solve.
 struct alignas(64) SolveRec {
     float a, b;                   // alpha, beta
     float lam;                    // ln B(alpha, beta) + ln min(alpha, beta), formed in FP64
     float us;                     // I_ts, as in EntryRec
     float maxl;                   // max_l
-    uint32_t pol;                 // 1: the draw takes the FP64 path (needs_polish)
+    uint32_t pol;                 // 1: a small shape (is_small_shape): its draws are deferred
     half2_t knot[2][kKnots];      // side 0 lower, 1 upper: (r_k, h * dr/du at u_k)
 };
 static_assert(sizeof(SolveRec) == 64, "SolveRec must stay one 64-byte line");
@@ -342,19 +342,23 @@ __host__ __device__ inline double inv_beta(double z, const EntryRec& E, InvBetaS
     return lower ? exp(yd) : -expm1(yd);
 }
 
-// Draws whose smaller shape parameter is below this take the FP64 polish; at
-// or above it the FP32 solve alone, with c0 formed in FP64, is within 1e-5
-// relative of the FP64 inverse (8e-6 at worst just above the threshold, 2e-6
-// in 99 of 100 draws): the quantile's sensitivity to an error in ln I grows
-// like 1/shape, most of all near t_s, where the terms of ln I cancel.
-constexpr double kPolishShape = 0.15;
-// The same threshold for solves that start from the entry record alone (they
-// form c0 in FP32, whose error the quantile divides by the shape).
+// Draws of entries whose smaller shape parameter is below this are small-shape
+// draws: on the side whose leading shape is below it they take the series
+// form of the solve (inv_beta32_any), deferred in the plain kernel so that the
+// two forms do not split a solve wave.  At or above it the continued-fraction
+// FP32 solve, with c0 formed in FP64, is within 1e-5 relative of the FP64
+// inverse (5e-6 at worst, 2e-6 in 99 of 100 draws); the quantile's
+// sensitivity to an error in ln I grows like 1/shape, most of all near t_s,
+// where the terms of ln I cancel in that form (1e-5 is reached near 0.15).
+constexpr double kSmallShape = 0.2;
+// Below this the surrogate kernel's exact fallback, which solves from the
+// entry record (c0 in FP32, whose error the quantile divides by the shape),
+// takes the FP64 polish of inv_beta.
 constexpr double kPolishShapeEntry = 0.2;
 
-__host__ __device__ inline bool needs_polish(const EntryRec& E)
+__host__ __device__ inline bool is_small_shape(const EntryRec& E)
 {
-    return (E.a < E.b ? E.a : E.b) < kPolishShape;
+    return (E.a < E.b ? E.a : E.b) < kSmallShape;
 }
 
 // Knots of one side, nk of them at u_k = k/(nk-1): out[2k] = r_k and
@@ -424,7 +428,7 @@ __host__ __device__ inline SolveRec make_solve_rec(const EntryRec& E)
     R.lam = E.a == 0.0 ? 0.0f : (float)(E.lnB + log(E.a < E.b ? E.a : E.b));
     R.us = E.us;
     R.maxl = E.maxl;
-    R.pol = needs_polish(E) ? 1u : 0u;
+    R.pol = is_small_shape(E) ? 1u : 0u;
     for (int side = 0; side < 2; ++side) {
         float v[2 * kKnots];
         knot_side(E, side == 0, v);
@@ -488,7 +492,7 @@ __host__ __device__ inline void beta_cf32(float t, float A, float B, float eps, 
 // loop.  The loop stops once a step moves the quantile x by less than 1e-2
 // relative: cubic convergence leaves far less than the FP32 evaluation noise
 // in ln I, which sets the error in x on the shapes this path takes
-// (min(a, b) >= kPolishShape): below 1e-5 against the FP64 inverse.
+// (min(a, b) >= kSmallShape): below 1e-5 against the FP64 inverse.
 constexpr float kStopX = 1e-2f;
 
 template <bool ROUGH>
@@ -542,7 +546,7 @@ __host__ __device__ inline void tail_side(float code, float us, bool& lower, flo
     }
 }
 
-// FP32-only inverse for well-conditioned shapes (min(a, b) >= kPolishShape),
+// FP32-only inverse for well-conditioned shapes (min(a, b) >= kSmallShape),
 // started from the entry's table: inv_beta's log-space iteration with Halley's
 // correction and the hardware helpers above, given the draw's side and that
 // side's probability.  Device only.
@@ -578,6 +582,78 @@ __device__ inline float inv_beta32_code(float code, const SolveRec& R)
     float p;
     tail_side(code, R.us, lower, p);
     return inv_beta32_side(lower, p, R);
+}
+
+// ---------------------------------------------------------------------------
+// Small leading shape.  The hypergeometric form of I_t (DLMF 8.17(ii)),
+//   I_t(A, B) = t^A / (A B(A, B)) (1 + A S(t)),
+//   S(t) = sum_{n>=1} (1-B)(2-B)...(n-B) t^n / (n! (A+n)),
+// writes ln I_t - ln p = A y + c0 + ln(1 + A S) - ln p with every term of
+// order A near the root, where the continued-fraction form subtracts two
+// terms of order B t (B ln(1-t) and ln T) to leave that remainder: in FP32
+// their rounding, divided by the slope A, swamps the quantile near t_s.  With
+// the series, c0 formed in FP64 and ln p and the sum taken in FP64, the FP32
+// solve holds 1e-5 relative for any shape.  The series converges like t^n
+// (t <= 1.1 t_s on this side, and t_s <= 1/2 once A <= B).
+// ---------------------------------------------------------------------------
+__device__ inline float ln1p_as(float t, float A, float B)       // ln(1 + A S(t))
+{
+    float c = 1.0f, S = 0.0f;                                      // c = (1-B)_n t^n / n!
+    for (int n = 1; n <= 64; ++n) {
+        const float fn = (float)n;
+        c *= (fn - B) * t * f32_rcp(fn);
+        const float term = c * f32_rcp(A + fn);
+        S += term;
+        if (fabsf(term) <= 3e-8f * fabsf(S)) break;
+    }
+    return log1pf(A * S);
+}
+
+// Halley's iteration on y = ln t with that form: f' = A (1-t)^(B-1) / (1 + A S)
+// and f''/f' = A - (B-1) t/(1-t) - f' as in newton32.
+__device__ inline float newton32_small(float y, bool lower, float A, float B, double lnp, double c0, float ymax)
+{
+    const float yfloor = lower ? -110.0f : -40.0f;
+    for (int it = 0; it < 12 && y > yfloor; ++it) {
+        const float t = __expf(y);
+        const float w = 1.0f - t;
+        const float l1t = f32_log1m(t, w);
+        const float tw = t * f32_rcp(w);
+        const float lg = ln1p_as(t, A, B);
+        const float f = (float)(((double)A * (double)y + c0 - lnp) + (double)lg);
+        float dy = -f * f32_rcp(A * __expf((B - 1.0f) * l1t - lg));
+        const float hc = 0.5f * ((A - (B - 1.0f) * tw) * dy + f);
+        if (fabsf(hc) < 0.5f) dy *= f32_rcp(1.0f + hc);
+        const float yn = fminf(y + dy, ymax);
+        const float step = yn - y;
+        y = yn;
+        if (fabsf(step) * (lower ? 1.0f : tw) <= kStopX) break;
+    }
+    // the quantile itself through the accurate exp: __expf scales y by log2(e)
+    // in FP32 first, a relative error of |y| 2^-24 in x
+    return lower ? expf(y) : -expm1f(y);
+}
+
+// The solve of a draw with z in FP64 (any shape): the side's leading shape at
+// or above kSmallShape takes inv_beta32_side, a smaller one the series form,
+// with c0 from the entry's FP64 ln B (for two tiny shapes c0 is of order one
+// while the slope A is tiny, so even its FP32 rounding would show).
+__device__ inline float inv_beta32_any(double z, const EntryRec& E, const SolveRec& R)
+{
+    const bool lower = z <= (double)R.us;
+    const double p = lower ? z : 1.0 - z;
+    const float A = lower ? R.a : R.b;
+    if (A >= (float)kSmallShape) return inv_beta32_side(lower, (float)p, R);
+    const float B = lower ? R.b : R.a;
+    const double c0 = -(E.lnB + log(lower ? E.a : E.b));
+    const double lnp = log(p);
+    const float rA = f32_rcp(A);
+    const float ts = (A + 1.0f) * f32_rcp(A + B + 2.0f);
+    const float ymax = f32_ln(fminf(1.1f * ts, 0.5f * (1.0f + ts)));
+    const float lnpf = (float)lnp;
+    const float lnps = f32_ln(lower ? R.us : 1.0f - R.us);
+    const float r = table_residual(R, lower, A, lnpf, lnps, rA);
+    return newton32_small(fminf((lnpf - (float)c0) * rA + r, ymax), lower, A, B, lnp, c0, ymax);
 }
 
 // The same solve started from a corrected leading term, for callers that hold
@@ -701,7 +777,7 @@ __host__ __device__ inline float tab_inverse_code(float code, const TabRec& T)
 // (0, 1), not only the 2^-24 grid, reaches the FP32 solve as its tail code).
 __device__ inline double inv_beta_layer(double z, const EntryRec& E, const SolveRec& R)
 {
-    if (R.pol) return inv_beta(z, E, nullptr, &R);
+    if (R.pol) return E.a == 0.0 ? E.lnB / E.maxl : (double)inv_beta32_any(z, E, R);
     return (double)inv_beta32_code(tail_code(z), R);
 }
 
