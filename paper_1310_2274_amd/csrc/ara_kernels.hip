@@ -302,15 +302,15 @@ __device__ __attribute__((noinline)) double corr_z(uint32_t trial, uint32_t slot
 // are still deferred keeps its partial loss in a small ring of pending chunks
 // and takes its occurrence terms once the last of them lands.  Every sum is a
 // fixed function of the trial, so the result does not depend on the launch.
-// Four wavefronts per SIMD (128 VGPRs): a fifth would leave 96, and the
-// spills that forces cost more than the occupancy gains.
+// Five wavefronts per SIMD (96 VGPRs, a few spilled; LDS allows five and a
+// half): four ran 10% slower, six (80 VGPRs) spill more than they gain.
 constexpr int kDefer = 128;                  // deferred-draw ring per wave (power of two)
 constexpr int kRing = 4;                     // chunks that may wait for deferred draws (four register sums)
 constexpr int kFinal = 0x7FFF;               // pending count of a finished (or empty) slot
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
 
 template <bool HAS_CORR, int WPB, bool TAB>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 4))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
     __shared__ uint32_t qidx[WPB][kQueue];
@@ -395,29 +395,25 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
             }
-            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-            int n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-            for (int i = 0; i < m; ++i) {
-                const uint32_t ki = (uint32_t)__builtin_amdgcn_readlane((int)key, i);
-                const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-                const bool own = (int)(ki & 63u) == lane;
-                const float add = own ? vi : 0.0f;
-                const int cnt = own ? 1 : 0;
-                switch ((ki >> 6) & (uint32_t)(kRing - 1)) {
-                    case 0: a0 += add; n0 += cnt; break;
-                    case 1: a1 += add; n1 += cnt; break;
-                    case 2: a2 += add; n2 += cnt; break;
-                    default: a3 += add; n3 += cnt; break;
+            // one ring slot at a time: the values bound for it (a ballot), in
+            // queue order, each added by the lane that owns its event slot
+            for (int rs = 0; rs < kRing; ++rs) {
+                uint64_t mk = __ballot(lane < m && ((key >> 6) & (uint32_t)(kRing - 1)) == (uint32_t)rs);
+                if (mk == 0ull) continue;
+                float a = 0.0f;
+                int cnt = 0;
+                while (mk != 0ull) {
+                    const int i = __builtin_ctzll(mk);
+                    mk &= mk - 1ull;
+                    const uint32_t ki = (uint32_t)__builtin_amdgcn_readlane((int)key, i);
+                    const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+                    const bool own = (int)(ki & 63u) == lane;
+                    a += own ? vi : 0.0f;
+                    cnt += own ? 1 : 0;
                 }
+                PC[rs][lane] += a;
+                PN[rs][lane] -= cnt;
             }
-            PC[0][lane] += a0;
-            PN[0][lane] -= n0;
-            PC[1][lane] += a1;
-            PN[1][lane] -= n1;
-            PC[2][lane] += a2;
-            PN[2][lane] -= n2;
-            PC[3][lane] += a3;
-            PN[3][lane] -= n3;
             dh = __builtin_amdgcn_readfirstlane((dh + m) & (kDefer - 1));
             dn = __builtin_amdgcn_readfirstlane(dn - m);
             wave_sync();
