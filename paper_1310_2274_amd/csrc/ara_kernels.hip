@@ -325,6 +325,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
     __shared__ float pcs[WPB][kRing][64];
     __shared__ short pns[WPB][kRing][64];
     __shared__ int rchunk[WPB][kRing];
+    __shared__ int tags[WPB][64];
     const int w = threadIdx.x >> 6;
     const int lane = lane_id();
     const int64_t trial = t0 + (int64_t)blockIdx.x * WPB + w;
@@ -341,6 +342,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
     float (*PC)[64] = pcs[w];        // pending chunks: partial event loss per slot
     short (*PN)[64] = pns[w];        //   deferred draws outstanding per slot
     int* RC = rchunk[w];             //   chunk held by each ring slot (-1: free)
+    int* TG = tags[w];               // flush: the queue position handed over next, per owner lane
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     int64_t row;
@@ -377,10 +379,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             if (settled && lane == 0) RC[r] = -1;
             wave_sync();
         };
-        // Evaluate the m <= 64 oldest deferred draws, one per lane, then hand
-        // each value, in queue order, to the lane that owns its slot: the
-        // owner sums its values per ring slot in registers and adds each sum
-        // to the slot's partial loss.
+        // Evaluate the m <= 64 oldest deferred draws, one per lane, then add
+        // each value to the partial loss of its event slot's ring entry.
         auto flush = [&](int m, int open_ring) {
             const int e = (dh + lane) & (kDefer - 1);
             float v = 0.0f;
@@ -395,24 +395,24 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 const float4 jt = L.jt[j];
                 v = jt.z * xl(loss, jt.x, jt.y);
             }
-            // one ring slot at a time: the values bound for it (a ballot), in
-            // queue order, each added by the lane that owns its event slot
-            for (int rs = 0; rs < kRing; ++rs) {
-                uint64_t mk = __ballot(lane < m && ((key >> 6) & (uint32_t)(kRing - 1)) == (uint32_t)rs);
-                if (mk == 0ull) continue;
-                float a = 0.0f;
-                int cnt = 0;
-                while (mk != 0ull) {
-                    const int i = __builtin_ctzll(mk);
-                    mk &= mk - 1ull;
-                    const uint32_t ki = (uint32_t)__builtin_amdgcn_readlane((int)key, i);
-                    const float vi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
-                    const bool own = (int)(ki & 63u) == lane;
-                    a += own ? vi : 0.0f;
-                    cnt += own ? 1 : 0;
+            // each value goes to its event slot's partial loss in rounds: per
+            // round one value per owner lane, the pending one latest in the queue
+            // (an LDS max over the lanes), so no two adds of a round meet; an
+            // owner with k values in the flush takes k rounds (most take one)
+            const uint32_t own_i = key & 63u, rs_i = (key >> 6) & (uint32_t)(kRing - 1);
+            bool pend = lane < m;
+            while (__ballot(pend) != 0ull) {
+                if (pend) TG[own_i] = -1;
+                wave_sync();
+                if (pend) atomicMax(&TG[own_i], lane);
+                wave_sync();
+                const bool win = pend && TG[own_i] == lane;
+                if (win) {
+                    PC[rs_i][own_i] += v;
+                    PN[rs_i][own_i] -= 1;
                 }
-                PC[rs][lane] += a;
-                PN[rs][lane] -= cnt;
+                wave_sync();
+                pend = pend && !win;
             }
             dh = __builtin_amdgcn_readfirstlane((dh + m) & (kDefer - 1));
             dn = __builtin_amdgcn_readfirstlane(dn - m);
