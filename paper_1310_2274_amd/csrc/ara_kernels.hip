@@ -308,6 +308,7 @@ constexpr int kDefer = 128;                  // deferred-draw ring per wave (pow
 constexpr int kRing = 4;                     // chunks that may wait for deferred draws (four register sums)
 constexpr int kFinal = 0x7FFF;               // pending count of a finished (or empty) slot
 constexpr float kDeferred = -1.0f;           // queue value of a deferred draw (losses are >= 0)
+constexpr int kRemDefer = 24;                // an FP32 list this short joins the deferred ring
 
 template <bool HAS_CORR, int WPB, bool TAB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
@@ -456,6 +457,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
             const uint32_t rw = rr.w;
             int remaining = row_count(rw);
             int rank = 0;
+            bool first_round = true;         // wave-uniform
             float c = 0.0f;                  // this event's loss across XELTs, deferred draws aside
             int pend = 0;                    // its deferred draws
             while (true) {
@@ -509,6 +511,28 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     wave_sync();
                     if (dn >= 64) flush(64, r);
                 }
+                // A chunk whose first round's FP32 list is short (sparse layers: a
+                // few draws per chunk) sends it to the deferred ring, which solves
+                // in full waves across chunks, instead of solving a nearly empty
+                // wave here.  In dense chunks, and in the short later rounds of
+                // events with many hits, the ring costs more than the partial wave
+                // it would save.  (Correlated layers keep it: the ring would need
+                // each draw's z in FP64.)
+                if (!HAS_CORR && !TAB && first_round && n32 != 0 && n32 <= kRemDefer) {
+                    const int rem = n32, n0 = 0;
+                    if (lane < rem) {
+                        const int q = L32[n0 + lane];
+                        const uint32_t meta = QM[q];
+                        const int e = (dh + dn + lane) & (kDefer - 1);
+                        DI[e] = QI[q];
+                        DM[e] = ((uint32_t)base + (meta & 63u)) | ((meta >> 8) << 24);
+                        QV[q] = kDeferred;
+                    }
+                    dn = __builtin_amdgcn_readfirstlane(dn + rem);
+                    n32 = n0;
+                    wave_sync();
+                    if (dn >= 64) flush(64, r);
+                }
                 // (B) FP32 solve
                 for (int b0 = 0; b0 < n32; b0 += 64) {
                     const int idx = b0 + lane;
@@ -538,6 +562,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                 }
                 rank += take;
                 remaining -= take;
+                first_round = false;
                 wave_sync();
             }
             // the chunk's rounds are over: slots with nothing deferred settle now

@@ -106,6 +106,21 @@ def test_plain_layer_under_sanitizers(drivers, sanitizer):
     assert np.any(y > 0)
 
 
+@pytest.mark.parametrize("sanitizer", ["address", "thread"])
+def test_sparse_plain_layer_under_sanitizers(drivers, sanitizer):
+    # a sparse layer (about 0.15 draws per occurrence): most chunks' FP32 lists
+    # are short and go to the deferred ring with the small-shape draws, so
+    # the ring flushes draws of many chunks at once and the pending ring fills
+    wl = synth.custom(6, 1000, 20000, 3, 800, 1200, seed=35)
+    lay = wl.layers[0]
+    ev = wl.yet()
+    y, om, _, _ = _run(drivers[sanitizer], ev.ravel(), None, wl.n_trials, wl.events_per_trial,
+                       wl.catalog_size, lay, 11, MODE_PLAIN)
+    yo, g, omo = oracle.run_layer(lay, ev, np.arange(wl.n_trials), wl.catalog_size, 11)
+    _check(y, om, yo, g, omo)
+    assert np.any(y > 0) or np.any(om > 0)
+
+
 def test_correlated_csr_hashed_under_asan(drivers):
     # correlated std (FP64 z kept in the deferred ring), variable-length trials
     # (one empty), and the hashed layer table
