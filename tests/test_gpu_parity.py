@@ -217,6 +217,8 @@ def test_tiny_workload_full_ylt(eng, mode):
     (33, 130, 200, 40, 30, 120, 0.0),     # 40 XELTs: several drain rounds per slot
     (40, 70, 120, 64, 40, 90, 0.0),       # 64 XELTs, dense hits
     (50, 90, 500, 5, 100, 300, 0.6),      # correlated std (section 3.2 five steps)
+    (400, 700, 40000, 2, 800, 1200, 0.0), # sparse (0.05 draws per occurrence): short FP32 lists go to the ring
+    (300, 500, 30000, 2, 600, 900, 0.5),  # sparse and correlated: they stay in the chunk
 ])
 def test_ragged_shapes(eng, N, K, C, J, lo, hi, sc):
     wl = synth.custom(N, K, C, J, lo, hi, seed=N * 7 + J, sigma_c_frac=sc)
