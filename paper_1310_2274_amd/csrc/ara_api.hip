@@ -980,6 +980,7 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
     if (in_bytes) HIPCHK(c, hipMemcpyAsync(c->ws_in.p, bs.host, in_bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipEventRecord(bs.done, c->stream));
     bs.pending = true;
+    const size_t first = c->elts.size();
     for (int j = 0; j < n_elts; ++j) {
         const ara_elt_desc& d = elts[j];
         EltRec e;
@@ -995,11 +996,23 @@ ara_status ara_load_elts(ara_ctx* c, int32_t C, const ara_elt_desc* elts, int32_
         if ((st = dev_alloc(c, e.idx, (size_t)C * 4)) || (st = dev_alloc(c, e.ent, n * sizeof(EntryRec))) ||
             (st = dev_alloc(c, e.mean, n * 8)) || (e.has_corr && (st = dev_alloc(c, e.cw, n * 8))) ||
             (st = dev_alloc(c, e.sol, n * sizeof(SolveRec)))) {
+            // a refused load changes nothing: the XELTs this call loaded go
+            // too, and the next call is ordered behind the work queued for them
             dev_free(c, e.idx);
             dev_free(c, e.ent);
             dev_free(c, e.mean);
             dev_free(c, e.cw);
             dev_free(c, e.sol);
+            for (size_t k = first; k < c->elts.size(); ++k) {
+                EltRec& x = c->elts[k];
+                dev_free(c, x.idx);
+                dev_free(c, x.ent);
+                dev_free(c, x.mean);
+                dev_free(c, x.cw);
+                dev_free(c, x.sol);
+            }
+            c->elts.resize(first);
+            (void)end_call(c, c->stream);
             return st;
         }
         char* q = (char*)c->ws_in.p + at[j];

@@ -478,6 +478,34 @@ def test_hbm_budget_refusal():
         assert h >= 0
 
 
+def test_refused_xelt_load_changes_nothing():
+    # five XELTs over a 600,000-event catalog (2.4 MB of index each) against an
+    # 8 MB budget: the fourth is refused, and the three loaded before it go too
+    torch_cuda()
+    C = 600_000
+    rng = np.random.default_rng(8)
+    elts = []
+    for k in range(5):
+        ids = np.sort(rng.choice(C, 1000, replace=False)).astype(np.int32)
+        mu = rng.lognormal(10, 1, 1000)
+        elts.append(synth.ELT(ids, mu, 0.5 * mu, None, 5 * mu, 0.0, math.inf, 1.0))
+    with P.Engine(0, hbm_budget_bytes=8 << 20) as e:
+        with pytest.raises(P.AraError) as ex:
+            P.ara_load_elts(e.ctx, C, elts)
+        assert ex.value.status == P.ARA_E_BUDGET
+        # the three XELTs loaded before the refusal were released (their blocks
+        # stay pooled for reuse): three fit again, a fourth still does not
+        hs = P.ara_load_elts(e.ctx, C, elts[:3])
+        with pytest.raises(P.AraError):
+            P.ara_load_elts(e.ctx, C, elts[3:4])
+        # and the XELTs that did load hold the right parameters
+        a, b = P.ara_elt_params(e.ctx, hs[2], 1000)
+        ao, bo = np.array([oracle.beta_params(m, s_, x)[:2] for m, s_, x in
+                           zip(elts[2].mean, elts[2].sigma_i, elts[2].max_loss)]).T
+        np.testing.assert_allclose(a, ao, rtol=1e-12)
+        np.testing.assert_allclose(b, bo, rtol=1e-12)
+
+
 def test_trial_tile_does_not_change_results_and_autotune(eng):
     torch = torch_cuda()
     wl = synth.portfolio(n_layers=3, n_trials=2000)
