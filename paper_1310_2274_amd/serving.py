@@ -11,7 +11,9 @@ A request is complete once the cursor has covered all N trials since it
 joined (wrapping around); its PML/TVaR are then computed on the device and
 its memory released for waiting requests.  Each trial's year loss depends only
 on the trial, the layer and the request's seed, so a result is the same alone
-and in any mix.
+and in any mix.  A request can be cancelled, or given a deadline after its
+arrival: either way it leaves the server with its memory released and no
+result, and the others are unaffected.
 """
 from __future__ import annotations
 
@@ -33,7 +35,9 @@ class Request:
     layer: object                 # synth.Layer-like: elts, terms, program_id
     seed: int
     arrival: float = 0.0          # seconds since the start of the run
+    deadline: float = math.inf    # seconds after arrival; past it the request is dropped
     # filled by the server
+    status: str = "waiting"       # waiting, active, done, cancelled or timed_out
     elt_handles: List[int] = field(default_factory=list)
     prepared: int = -1
     ylt: object = None            # torch tensor [N] on the device
@@ -83,6 +87,7 @@ class PricingServer:
         self.waiting: collections.deque = collections.deque()
         self.active: List[Request] = []
         self.finished: List[Request] = []
+        self.dropped: List[Request] = []            # cancelled or timed out
         self.refusals = 0
         self.ticks = 0
         self.t0 = time.perf_counter()
@@ -92,7 +97,38 @@ class PricingServer:
         return time.perf_counter() - self.t0
 
     def submit(self, req: Request) -> None:
+        req.status = "waiting"
         self.waiting.append(req)
+
+    def cancel(self, req_id: int, status: str = "cancelled") -> bool:
+        """Drop a waiting or active request: its layer tables and YLT are
+        released at once (work already queued for it completes first on the
+        device, ordered by the library), and it finishes with no result."""
+        for r in list(self.waiting):
+            if r.req_id == req_id:
+                self.waiting.remove(r)
+                self._drop(r, status)
+                return True
+        for r in self.active:
+            if r.req_id == req_id:
+                self.active.remove(r)
+                ara_free_layer(self.ctx, r.prepared)
+                r.prepared = -1
+                self.used -= r.bytes
+                r.ylt = None
+                self._drop(r, status)
+                return True
+        return False
+
+    def _drop(self, r: Request, status: str) -> None:
+        r.status = status
+        r.finished_at = self.now()
+        self.dropped.append(r)
+
+    def _expire(self) -> None:
+        now = self.now()
+        for r in [r for r in list(self.waiting) + self.active if now > r.arrival + r.deadline]:
+            self.cancel(r.req_id, status="timed_out")
 
     def _admit(self) -> None:
         while self.waiting and len(self.active) < self.max_active:
@@ -125,14 +161,16 @@ class PricingServer:
             req.start = self.cursor
             req.done = 0
             req.admitted_at = self.now()
+            req.status = "active"
             self.used += need
             self.waiting.popleft()
             self.active.append(req)
 
     # ------------------------------------------------------------ one tick
     def tick(self) -> None:
-        """Admit what fits, then evaluate the current trial tile for every
-        active request in one launch."""
+        """Drop what is past its deadline, admit what fits, then evaluate the
+        current trial tile for every active request in one launch."""
+        self._expire()
         self._admit()
         if not self.active:
             return
@@ -164,6 +202,7 @@ class PricingServer:
         pml, tvar = ara_risk_measures(self.ctx, r.ylt, self.rps)    # waits for the request's last tile
         self.inflight.clear()                                         # ... and every tick before it
         r.pml, r.tvar = pml, tvar
+        r.status = "done"
         r.finished_at = self.now()
         ara_free_layer(self.ctx, r.prepared)
         self.used -= r.bytes

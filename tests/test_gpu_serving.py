@@ -94,3 +94,26 @@ def test_served_request_matches_oracle(setup):
     trials = np.array([0, 1, 6999, 7000, 13999, N - 1])
     yo, g, _ = oracle.run_layer(layers[2], yet[trials], trials, C, 31337)
     assert_ylt_close(r.ylt.cpu().numpy()[trials].astype(np.float64), yo, g, "served request")
+
+
+def test_cancel_and_deadline(setup):
+    # a request cancelled while on the GPU and one past its deadline before
+    # admission leave with no result and their memory released; the others'
+    # results are unchanged
+    torch, eng, yh, yet, layers = setup
+    srv = serving.PricingServer(eng, yh, N, K, C, P.MODE_PLAIN, hbm_budget_bytes=8 << 30, tile=3000)
+    reqs = [serving.Request(i, lay, seed=300 + i) for i, lay in enumerate(layers[:4])]
+    reqs[3].deadline = 0.0
+    for r in reqs:
+        srv.submit(r)
+    srv.tick()
+    srv.tick()
+    assert reqs[1].status == "active" and reqs[3].status == "timed_out"
+    assert srv.cancel(1) and not srv.cancel(1) and not srv.cancel(99)
+    while srv.waiting or srv.active:
+        srv.tick()
+    assert {r.req_id: r.status for r in srv.finished + srv.dropped} == \
+        {0: "done", 1: "cancelled", 2: "done", 3: "timed_out"}
+    assert srv.used == 0 and reqs[1].ylt is None and reqs[1].pml is None
+    for r in srv.finished:
+        assert np.array_equal(r.ylt.cpu().numpy(), alone(torch, eng, yh, r.layer, r.seed, P.MODE_PLAIN))
