@@ -191,9 +191,10 @@ ara_status ara_yelt_increments(ara_ctx *ctx, int32_t yet_handle, int64_t trial_b
 ara_status ara_elt_params(ara_ctx *ctx, int32_t elt_handle, double *alpha_out, double *beta_out);
 
 /*
- * A batch of layers over one YET in one launch: each trial tile's event ids
- * are read from HBM once and evaluated for every layer.  ylt_outs[l] receives
- * layer l's YLT (device pointers only).
+ * A batch of layers over one YET in one launch: one wavefront evaluates its
+ * trial for every layer in turn, re-reading the trial's event ids (4 KB) per
+ * layer from the caches.  ylt_outs[l] receives layer l's YLT (device pointers
+ * only).
  */
 ara_status ara_run_layers(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layers,
                           int32_t n_layers, ara_mode mode, uint32_t seed,
