@@ -191,10 +191,12 @@ ara_status ara_yelt_increments(ara_ctx *ctx, int32_t yet_handle, int64_t trial_b
 ara_status ara_elt_params(ara_ctx *ctx, int32_t elt_handle, double *alpha_out, double *beta_out);
 
 /*
- * A batch of layers over one YET in one launch: one wavefront evaluates its
- * trial for every layer in turn, re-reading the trial's event ids (4 KB) per
- * layer from the caches.  ylt_outs[l] receives layer l's YLT (device pointers
- * only).
+ * A batch of layers over one YET: the layers go to the GPU in groups whose
+ * tables together stay within 24 MB (consecutive in the given order, one
+ * launch per group, so a group's solve records stay in the caches); one
+ * wavefront takes its trial through every layer of its group, re-reading the
+ * trial's event ids per layer.  ylt_outs[l] receives layer l's YLT (device
+ * pointers only).
  */
 ara_status ara_run_layers(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc *layers,
                           int32_t n_layers, ara_mode mode, uint32_t seed,
@@ -204,7 +206,8 @@ ara_status ara_run_layers(ara_ctx *ctx, int32_t yet_handle, const ara_layer_desc
  * Prepared layers: the layer tables of `layer` for `mode` are built once and
  * kept (they no longer refer to the XELTs, which may be freed).
  * ara_run_prepared evaluates n prepared layers (all of one mode) over trials
- * [trial_begin, trial_end) in one launch, each with its own seed, writing
+ * [trial_begin, trial_end), grouped into launches as ara_run_layers groups
+ * them, each with its own seed, writing
  * ylt_outs[l][i - trial_begin] (device pointers) and, where max_occ_outs is not
  * NULL and its entry not NULL, the largest occurrence loss per trial.
  * Results are those of ara_run_layer_ex for each layer alone.
