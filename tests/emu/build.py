@@ -11,9 +11,11 @@ AddressSanitizer checks every device and LDS access and ThreadSanitizer
 reports any cross-lane LDS access that no wave_sync / __syncthreads orders.
 Host compiler only: no GPU code is built here.
 """
+import fcntl
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
@@ -22,20 +24,26 @@ CXX = os.environ.get("EMU_CXX", "/opt/rocm/llvm/bin/clang++")
 
 
 def build(sanitizer: str, out: str = "") -> str:
+    """Compile and link the driver; safe to call from several processes at
+    once (pytest-xdist workers): one build per output at a time, objects in
+    a private directory, and the executable replaced in one rename."""
     assert sanitizer in ("address", "thread")
     out = out or os.path.join(HERE, f"emu_driver_{sanitizer}")
     srcs = [os.path.join(CSRC, f) for f in ("ara_api.hip", "ara_kernels.hip", "ara_surrogate.hip")]
     cmd = [CXX, "-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer", f"-fsanitize={sanitizer}",
            "-Wno-unknown-attributes", "-Wno-ignored-attributes", "-Wno-unused-result",
            "-I", HERE, "-I", os.path.join(ROOT, "include"), "-pthread"]
-    objs = []
-    for s in srcs + [os.path.join(HERE, "emu_runtime.cpp"), os.path.join(HERE, "emu_driver.cpp")]:
-        o = out + "_" + os.path.basename(s) + ".o"
-        subprocess.check_call(cmd + ["-x", "c++", "-c", s, "-o", o])
-        objs.append(o)
-    subprocess.check_call([CXX, f"-fsanitize={sanitizer}", "-pthread", "-o", out] + objs)
-    for o in objs:
-        os.remove(o)
+    with open(out + ".lock", "w") as lock:
+        fcntl.flock(lock, fcntl.LOCK_EX)
+        with tempfile.TemporaryDirectory(dir=os.path.dirname(out)) as tmp:
+            objs = []
+            for s in srcs + [os.path.join(HERE, "emu_runtime.cpp"), os.path.join(HERE, "emu_driver.cpp")]:
+                o = os.path.join(tmp, os.path.basename(s) + ".o")
+                subprocess.check_call(cmd + ["-x", "c++", "-c", s, "-o", o])
+                objs.append(o)
+            exe = os.path.join(tmp, "driver")
+            subprocess.check_call([CXX, f"-fsanitize={sanitizer}", "-pthread", "-o", exe] + objs)
+            os.replace(exe, out)
     return out
 
 
