@@ -191,9 +191,10 @@ ara_status ara_yelt_increments(ara_ctx *ctx, int32_t yet_handle, int64_t trial_b
 ara_status ara_elt_params(ara_ctx *ctx, int32_t elt_handle, double *alpha_out, double *beta_out);
 
 /*
- * A batch of layers over one YET: the layers go to the GPU in groups whose
- * tables together stay within 24 MB (consecutive in the given order, one
- * launch per group, so a group's solve records stay in the caches); one
+ * A batch of layers over one YET: in the plain and table modes the layers go
+ * to the GPU in groups whose tables together stay within 24 MB (consecutive
+ * in the given order, one launch per group, so a group's solve records stay
+ * in the caches; the mean and surrogate modes take the batch in one launch); one
  * wavefront takes its trial through every layer of its group, re-reading the
  * trial's event ids per layer.  ylt_outs[l] receives layer l's YLT (device
  * pointers only).

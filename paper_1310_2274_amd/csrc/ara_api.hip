@@ -396,7 +396,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p, int32_t kind)
         b += align256(slots * 32);
     }
     if (p.has_corr) b += align256(p.total * 8);
-    if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
+    if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec)) + align256(p.total * 8);
     if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
     return b;
@@ -430,9 +430,12 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         q += align256(p.total * 8);
     }
     SolveRec* psol = nullptr;
+    float2* pthr = nullptr;
     if (mode == ARA_MODE_PLAIN) {
         psol = (SolveRec*)q;
         q += align256(p.total * sizeof(SolveRec));
+        pthr = (float2*)q;
+        q += align256(p.total * 8);
     }
     HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
     HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
@@ -441,12 +444,13 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         ptab = (TabRec*)q;
         q += align256(p.total * sizeof(TabRec));
     }
-    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, ptab, s));
+    HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, pthr, ptab, s));
     p.dev.rows = rows;
     p.dev.hbits = 0;
     p.dev.pent = pent;
     p.dev.pcw = pcw;
     p.dev.psol = psol;
+    p.dev.pthr = pthr;
     p.dev.ptab = ptab;
     if (mode == ARA_MODE_SURROGATE) {
         SurEntry* psur = (SurEntry*)q;
@@ -524,17 +528,17 @@ ara_status launch_mode(ara_ctx* c, int mode, bool has_corr, YetRec& yr, const Ye
     else if (mode == ARA_MODE_MEAN)
         HIPCHK(c, launch_mean(yd, t0, t1, layers_dev, n_layers, (const uint16_t*)yr.sev.p, (const uint32_t*)yr.soff.p,
                               (const uint32_t*)yr.scnt.p, c->ws_mean.p, yelt, s));
-    else if (!group_bytes || n_layers == 1)
-        HIPCHK(c, launch_layers(mode, has_corr, yd, t0, t1, layers_dev, n_layers, c->wpb[mode], s));
     else {
         for (int32_t g0 = 0; g0 < n_layers;) {
-            uint64_t acc = (*group_bytes)[(size_t)g0];
-            bool corr = (*group_corr)[(size_t)g0];
-            int32_t g1 = g0 + 1;
-            while (g1 < n_layers && acc + (*group_bytes)[(size_t)g1] <= kGroupTableBytes) {
-                acc += (*group_bytes)[(size_t)g1];
-                corr = corr || (*group_corr)[(size_t)g1];
-                ++g1;
+            int32_t g1 = n_layers;
+            bool corr = has_corr;
+            if (group_bytes) {
+                uint64_t acc = (*group_bytes)[(size_t)g0];
+                corr = (*group_corr)[(size_t)g0];
+                for (g1 = g0 + 1; g1 < n_layers && acc + (*group_bytes)[(size_t)g1] <= kGroupTableBytes; ++g1) {
+                    acc += (*group_bytes)[(size_t)g1];
+                    corr = corr || (*group_corr)[(size_t)g1];
+                }
             }
             HIPCHK(c, launch_layers(mode, corr, yd, t0, t1, layers_dev + g0, g1 - g0, c->wpb[mode], s));
             g0 = g1;

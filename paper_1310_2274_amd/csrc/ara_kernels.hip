@@ -108,7 +108,7 @@ __global__ void k_layer_count(int32_t C, int32_t J, const EltDev* __restrict__ e
 
 __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ elts, const uint32_t* __restrict__ off,
                              uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw,
-                             SolveRec* __restrict__ psol, TabRec* __restrict__ ptab)
+                             SolveRec* __restrict__ psol, float2* __restrict__ pthr, TabRec* __restrict__ ptab)
 {
     const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= C) return;
@@ -126,6 +126,7 @@ __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ el
         pent[o] = E;
         if (pcw) pcw[o] = X.cw ? X.cw[i] : make_float2(1.0f, 0.0f);
         if (psol) psol[o] = X.solve[i];
+        if (pthr) pthr[o] = term_thresholds(E, X.ded, X.lim);
         if (ptab) ptab[o] = X.tab[i];
         if (rank < kRowPolBits && is_small_shape(E)) pol |= 1u << rank;
         ++o;
@@ -314,6 +315,7 @@ template <bool HAS_CORR, int WPB, bool TAB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
+    constexpr bool SKIP = !TAB;      // the plain mode skips draws whose term is fixed (term_thresholds)
     __shared__ uint32_t qidx[WPB][kQueue];
     __shared__ uint16_t qmeta[WPB][kQueue];
     __shared__ float qv[WPB][kQueue];
@@ -476,24 +478,43 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     QM[pos + i] = (uint16_t)(lane | (pol << 7) | (j << 8));
                 }
                 wave_sync();
-                // (A) classify: FP32 draws to the list, the others to the deferred ring
+                // (A) classify: draws whose term the quantile cannot change take
+                // it here; the other FP32 draws go to the list, the rest to the
+                // deferred ring
                 int n32 = 0;
                 for (int b0 = 0; b0 < total; b0 += 64) {
                     const int q = b0 + lane;
                     const bool in = q < total;
-                    bool pol = false;
-                    if (in) pol = (QM[q] & 0x80u) != 0u;
-                    const uint64_t b64 = __ballot(in && pol);
-                    const uint64_t b32 = __ballot(in && !pol);
-                    // correlated layers: the draw's z (two uniforms, normal transforms in
-                    // FP64) is formed here, once per draw in full waves, and kept for the solve
+                    bool pol = false, keep = in;
+                    // the draw's z is formed here, once per draw in full waves, and
+                    // kept for the solve (correlated layers: two uniforms and the
+                    // normal transforms in FP64)
                     double zc = 0.0;
-                    if (HAS_CORR && in) {
-                        const uint32_t pi = QI[q], meta = QM[q];
-                        const uint32_t own = meta & 63u;
-                        zc = corr_z(tr, (uint32_t)base + own, meta >> 8, L.seed, L.prog, L.pcw, pi, UC[own], QC[own]);
-                    }
                     if (in) {
+                        const uint32_t pi = QI[q], meta = QM[q];
+                        const uint32_t own = meta & 63u, j = meta >> 8;
+                        pol = (meta & 0x80u) != 0u;
+                        if (HAS_CORR)
+                            zc = corr_z(tr, (uint32_t)base + own, j, L.seed, L.prog, L.pcw, pi, UC[own], QC[own]);
+                        else if (SKIP)
+                            zc = draw_z<false>(tr, (uint32_t)base + own, j, L.seed, L.prog, nullptr, pi);
+                        if (SKIP) {
+                            // the loss would lie within the retention, or beyond
+                            // retention + limit: the term is 0 or the limit
+                            const float2 th = L.pthr[pi];
+                            if (zc <= (double)th.x) {
+                                QV[q] = 0.0f;
+                                keep = false;
+                            } else if (zc >= (double)th.y) {
+                                const float4 jt = L.jt[j];
+                                QV[q] = jt.z * jt.y;
+                                keep = false;
+                            }
+                        }
+                    }
+                    const uint64_t b64 = __ballot(keep && pol);
+                    const uint64_t b32 = __ballot(keep && !pol);
+                    if (keep) {
                         if (pol) {
                             const int e = (dh + dn + __popcll(b64 & below)) & (kDefer - 1);
                             const uint32_t meta = QM[q];
@@ -504,6 +525,7 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         } else {
                             L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
                             if (HAS_CORR) QV[q] = tail_code(zc);      // the FP32 solve takes z as its tail code
+                            else if (SKIP) QV[q] = (float)zc;         // on the 2^-24 grid: exact
                         }
                     }
                     n32 = __builtin_amdgcn_readfirstlane(n32 + __popcll(b32));
@@ -541,7 +563,8 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
                         // uncorrelated draws are on the 2^-24 grid; correlated ones arrive as tail codes
-                        const float z = HAS_CORR ? QV[q] : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
+                        const float z = (HAS_CORR || SKIP) ? QV[q]
+                                                           : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
                         float loss;
                         if (TAB) {
                             const TabRec& T = L.ptab[pi];
@@ -1136,9 +1159,11 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
 }
 
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, SolveRec* psol, TabRec* ptab, hipStream_t s)
+                             EntryRec* pent, float2* pcw, SolveRec* psol, float2* pthr, TabRec* ptab,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol, ptab);
+    hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol,
+                       pthr, ptab);
     return hipGetLastError();
 }
 

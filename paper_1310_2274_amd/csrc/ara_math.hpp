@@ -146,6 +146,56 @@ __host__ __device__ inline double beta_inc_lower(double t, double A, double B, d
     return exp(A * log(t) + B * log1p(-t) - lnB) / A * (den / num);
 }
 
+// I_t(a, b) in FP64 for any t: the lower fraction below t_s, the reflection
+// I_t(a, b) = 1 - I_{1-t}(b, a) above it.
+__host__ __device__ inline double beta_inc(double t, const EntryRec& E)
+{
+    if (t <= 0.0) return 0.0;
+    if (t >= 1.0) return 1.0;
+    const double ts = (E.a + 1.0) / (E.a + E.b + 2.0);
+    return t <= ts ? beta_inc_lower(t, E.a, E.b, E.lnB) : 1.0 - beta_inc_lower(1.0 - t, E.b, E.a, E.lnB);
+}
+
+// float(v) rounded toward -inf / +inf.
+__host__ __device__ inline float f32_down(double v)
+{
+    const float f = (float)v;
+    return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__host__ __device__ inline float f32_up(double v)
+{
+    const float f = (float)v;
+    return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+
+// The draws of an entry whose per-XELT term does not depend on the quantile
+// (section 2.3's financial terms I on the sampled loss of section 3.3): a
+// loss l = max_l x at most the retention nets to 0, one at least retention +
+// limit nets to the limit, and x <= t  <=>  z <= I_t(alpha, beta).  Returns
+// (lo, hi): z <= lo gives 0, z >= hi the limit.  Both come from FP64
+// probabilities, widened by 1e-10 relative (far above their rounding) and
+// rounded outward to float, so a draw is skipped only where its loss
+// certainly lies beyond the threshold; draws inside the margin are solved.
+// A degenerate entry's loss is its mean (lnB): always one side or never.
+__host__ __device__ inline float2 term_thresholds(const EntryRec& E, double ret, double lim)
+{
+    float lo = -1.0f, hi = 2.0f;                         // z is in (0, 1): never
+    if (E.a == 0.0) {
+        if (E.lnB <= ret) lo = 1.0f;
+        else if (E.lnB >= ret + lim) hi = 0.0f;
+        return make_float2(lo, hi);
+    }
+    const double m = (double)E.maxl;
+    const double tl = ret / m, th = (ret + lim) / m;
+    if (tl >= 1.0) return make_float2(1.0f, hi);         // every loss is within the retention
+    if (tl > 0.0) lo = f32_down(beta_inc(tl, E) * (1.0 - 1e-10));
+    if (th < 1.0) {
+        const double I = beta_inc(th, E);
+        hi = f32_up(I + (1.0 - I) * 1e-10);
+    }
+    return make_float2(lo, hi);
+}
+
 // ---------------------------------------------------------------------------
 // Inverse of the regularised incomplete beta: x with I_x(a,b) = z.
 //

@@ -532,3 +532,54 @@ def test_trial_tile_does_not_change_results_and_autotune(eng):
         for h in hs:
             P.ara_free_layer(eng.ctx, h)
         P.ara_set_trial_tile(eng.ctx, mode, 4)
+
+
+def _fixed_shape_elt(rng, C, n, a, b, q_lo, q_hi, sigma_c_frac=0.0, degenerate=None):
+    # every entry the same Beta(a, b) with max loss 1e6, so the XELT's
+    # retention and limit sit at the z quantiles q_lo and q_hi of every entry:
+    # the draws below q_lo net to 0 and those above q_hi to the limit without
+    # a solve, the ones between are solved
+    from scipy.special import betaincinv
+    ids = np.sort(rng.choice(C, size=n, replace=False)).astype(np.int32)
+    mx = np.full(n, 1e6)
+    mu = mx * a / (a + b)
+    sd = mx * math.sqrt(a * b / ((a + b) ** 2 * (a + b + 1.0)))
+    sd = np.full(n, sd)
+    if degenerate is not None:              # sigma = 0: the loss is the mean
+        sd = np.zeros(n)
+        mu = np.full(n, degenerate)
+    sc = None
+    if sigma_c_frac > 0.0:
+        sc, sd = sd * sigma_c_frac, sd * (1.0 - sigma_c_frac)
+    ded = 1e6 * float(betaincinv(a, b, q_lo)) if q_lo > 0.0 else 0.0
+    top = 1e6 * float(betaincinv(a, b, q_hi)) if q_hi < 1.0 else math.inf
+    return synth.ELT(ids, mu, sd, sc, mx, ded, top - ded, 0.75)
+
+
+@pytest.mark.parametrize("sigma_c_frac", [0.0, 0.4])
+def test_fixed_term_draws_vs_oracle(eng, sigma_c_frac):
+    # XELT terms at entry quantiles: in the plain mode a draw whose loss lies
+    # within the retention or beyond retention + limit takes its term without
+    # the inverse (term_thresholds); the year and occurrence losses must match
+    # the oracle, which solves every draw, trial by trial.  Small shapes (the
+    # deferred ring) and degenerate entries below, inside and above the terms
+    # are included.
+    rng = np.random.default_rng(43)
+    N, K, C = 300, 400, 900
+    wl = synth.custom(N, K, C, 7, 300, 600, seed=43)
+    lay = wl.layers[0]
+    lay.elts = [
+        _fixed_shape_elt(rng, C, 500, 2.0, 5.0, 0.5, 0.9, sigma_c_frac),
+        _fixed_shape_elt(rng, C, 400, 0.7, 3.0, 0.3, 0.99, sigma_c_frac),
+        _fixed_shape_elt(rng, C, 400, 4.0, 1.5, 0.0, 0.6, sigma_c_frac),
+        _fixed_shape_elt(rng, C, 300, 0.1, 2.0, 0.8, 0.97, sigma_c_frac),       # small shape
+        _fixed_shape_elt(rng, C, 300, 2.0, 5.0, 0.5, 0.9, degenerate=1e5),      # mean within the retention
+        _fixed_shape_elt(rng, C, 300, 2.0, 5.0, 0.1, 0.2, degenerate=4e5),      # mean beyond retention + limit
+        _fixed_shape_elt(rng, C, 300, 2.0, 5.0, 0.2, 0.9, degenerate=3e5),      # mean between
+    ]
+    lay.occ_retention, lay.occ_limit, lay.agg_retention, lay.agg_limit = 0.0, math.inf, 0.0, math.inf
+    y, om, _ = gpu_ylt(eng, wl, oracle.MODE_PLAIN, 19, with_omax=True)
+    yo, g, omo = oracle_ylt(wl, np.arange(N), oracle.MODE_PLAIN, 19)
+    assert_ylt_close(y, yo, g, f"fixed-term draws, sigma_c_frac={sigma_c_frac}")
+    assert_ylt_close(om, omo, g, "max occurrence")
+    assert np.all(y > 0)
