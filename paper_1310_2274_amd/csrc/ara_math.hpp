@@ -146,6 +146,8 @@ __host__ __device__ inline double beta_inc_lower(double t, double A, double B, d
     return exp(A * log(t) + B * log1p(-t) - lnB) / A * (den / num);
 }
 
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
 // I_t(a, b) in FP64 for any t: the lower fraction below t_s, the reflection
 // I_t(a, b) = 1 - I_{1-t}(b, a) above it.
 __host__ __device__ inline double beta_inc(double t, const EntryRec& E)
@@ -168,32 +170,52 @@ __host__ __device__ inline float f32_up(double v)
     return (double)f < v ? nextafterf(f, INFINITY) : f;
 }
 
+// half(v) rounded toward 0 / +inf, for 0 <= v <= 2 (a step of one in the
+// bit pattern is one unit in the last place for non-negative halves).
+__host__ __device__ inline _Float16 f16_down(float v)
+{
+    const _Float16 h = (_Float16)v;
+    return (float)h > v ? __builtin_bit_cast(_Float16, (uint16_t)(__builtin_bit_cast(uint16_t, h) - 1u)) : h;
+}
+__host__ __device__ inline _Float16 f16_up(float v)
+{
+    const _Float16 h = (_Float16)v;
+    return (float)h < v ? __builtin_bit_cast(_Float16, (uint16_t)(__builtin_bit_cast(uint16_t, h) + 1u)) : h;
+}
+
 // The draws of an entry whose per-XELT term does not depend on the quantile
 // (section 2.3's financial terms I on the sampled loss of section 3.3): a
 // loss l = max_l x at most the retention nets to 0, one at least retention +
 // limit nets to the limit, and x <= t  <=>  z <= I_t(alpha, beta).  Returns
-// (lo, hi): z <= lo gives 0, z >= hi the limit.  Both come from FP64
-// probabilities, widened by 1e-10 relative (far above their rounding) and
-// rounded outward to float, so a draw is skipped only where its loss
-// certainly lies beyond the threshold; draws inside the margin are solved.
-// A degenerate entry's loss is its mean (lnB): always one side or never.
-__host__ __device__ inline float2 term_thresholds(const EntryRec& E, double ret, double lim)
+// (lo, hi) in half precision: z <= lo gives 0, z >= hi the limit.  Both come
+// from FP64 probabilities, widened by 1e-10 relative (far above their
+// rounding) and rounded outward, so a draw is skipped only where its loss
+// certainly lies beyond the threshold; draws inside the margin (at most one
+// half-precision step, 2^-11 relative) are solved.  lo = 0 and hi = 2 never
+// skip (z > 0 and z < 1 on the uniform grid; a correlated z of exactly 0 has
+// x = 0); lo = 1 and hi = 0 always do.  A degenerate entry's loss is its mean
+// (lnB): always one side or never.  Four bytes per entry keep the table small
+// enough to stay in L2 beside the layer rows.
+__host__ __device__ inline half2_t term_thresholds(const EntryRec& E, double ret, double lim)
 {
-    float lo = -1.0f, hi = 2.0f;                         // z is in (0, 1): never
+    double lo = 0.0, hi = 2.0;
     if (E.a == 0.0) {
-        if (E.lnB <= ret) lo = 1.0f;
-        else if (E.lnB >= ret + lim) hi = 0.0f;
-        return make_float2(lo, hi);
+        if (E.lnB <= ret) lo = 1.0;
+        else if (E.lnB >= ret + lim) hi = 0.0;
+    } else {
+        const double m = (double)E.maxl;
+        const double tl = ret / m, th = (ret + lim) / m;
+        if (tl >= 1.0) lo = 1.0;                          // every loss is within the retention
+        else if (tl > 0.0) lo = beta_inc(tl, E) * (1.0 - 1e-10);
+        if (th < 1.0) {
+            const double I = beta_inc(th, E);
+            hi = I + (1.0 - I) * 1e-10;
+        }
     }
-    const double m = (double)E.maxl;
-    const double tl = ret / m, th = (ret + lim) / m;
-    if (tl >= 1.0) return make_float2(1.0f, hi);         // every loss is within the retention
-    if (tl > 0.0) lo = f32_down(beta_inc(tl, E) * (1.0 - 1e-10));
-    if (th < 1.0) {
-        const double I = beta_inc(th, E);
-        hi = f32_up(I + (1.0 - I) * 1e-10);
-    }
-    return make_float2(lo, hi);
+    half2_t r;
+    r.x = f16_down(f32_down(lo));
+    r.y = f16_up(f32_up(hi));
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,7 +308,6 @@ constexpr int kKnots = 5;
 constexpr float kLnPmin = -16.635532333438686f;      // ln 2^-24
 constexpr float kVmapShape = 3.0f;
 
-typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
 
 // One entry's record for the FP32 solve: the shapes and constants in FP32 and
 // both sides' start tables, one 64-byte line per draw.  Small-shape entries
