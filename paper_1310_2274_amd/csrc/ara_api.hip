@@ -396,7 +396,8 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p, int32_t kind)
         b += align256(slots * 32);
     }
     if (p.has_corr) b += align256(p.total * 8);
-    if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec)) + align256(p.total * 4);
+    if (mode == ARA_MODE_PLAIN || mode == ARA_MODE_TABLE) b += align256(p.total * 4);
+    if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
     if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
     return b;
@@ -434,6 +435,8 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
     if (mode == ARA_MODE_PLAIN) {
         psol = (SolveRec*)q;
         q += align256(p.total * sizeof(SolveRec));
+    }
+    if (mode == ARA_MODE_PLAIN || mode == ARA_MODE_TABLE) {
         pthr = (half2_t*)q;
         q += align256(p.total * 4);
     }

@@ -315,7 +315,7 @@ template <bool HAS_CORR, int WPB, bool TAB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
-    constexpr bool SKIP = !TAB;      // the plain mode skips draws whose term is fixed (term_thresholds)
+    constexpr bool SKIP = true;      // draws whose term is fixed skip the inverse (term_thresholds), in both modes
     __shared__ uint32_t qidx[WPB][kQueue];
     __shared__ uint16_t qmeta[WPB][kQueue];
     __shared__ float qv[WPB][kQueue];
