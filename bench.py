@@ -178,9 +178,11 @@ def oracle_errors(wl, pml, tvar):
 
 
 def surrogate_share(P, eng, handles, layer, occ, n=1_000_000, seed=5):
-    """Share of the pass's draws the network answers (the rest fall back to the
-    exact inverse): draws sampled in proportion to their entries' occurrence
-    counts, u uniform on the 2^-24 grid, answered by ara_surrogate_eval."""
+    """Share of draws the network answers (the rest fall back to the exact
+    inverse): draws sampled in proportion to their entries' occurrence counts,
+    u uniform on the 2^-24 grid, answered by ara_surrogate_eval.  The layer
+    pass gives draws whose XELT term is fixed their term without a quantile;
+    they are counted here like any other draw."""
     rng = np.random.default_rng(seed)
     a_all, b_all, w_all = [], [], []
     for h, e in zip(handles, layer.elts):

@@ -396,7 +396,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p, int32_t kind)
         b += align256(slots * 32);
     }
     if (p.has_corr) b += align256(p.total * 8);
-    if (mode == ARA_MODE_PLAIN || mode == ARA_MODE_TABLE) b += align256(p.total * 4);
+    if (mode != ARA_MODE_MEAN) b += align256(p.total * 4);
     if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
     if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
@@ -431,15 +431,12 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         q += align256(p.total * 8);
     }
     SolveRec* psol = nullptr;
-    half2_t* pthr = nullptr;
     if (mode == ARA_MODE_PLAIN) {
         psol = (SolveRec*)q;
         q += align256(p.total * sizeof(SolveRec));
     }
-    if (mode == ARA_MODE_PLAIN || mode == ARA_MODE_TABLE) {
-        pthr = (half2_t*)q;
-        q += align256(p.total * 4);
-    }
+    half2_t* pthr = (half2_t*)q;           // every sampling mode
+    q += align256(p.total * 4);
     HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
     HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
     TabRec* ptab = nullptr;

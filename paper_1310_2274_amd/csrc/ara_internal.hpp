@@ -43,7 +43,7 @@ struct LayerDev {
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
     const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
-    const half2_t* pthr;    // [sum n_j] plain and table modes: (lo, hi) of term_thresholds for the entry's XELT
+    const half2_t* pthr;    // [sum n_j] sampling modes: (lo, hi) of term_thresholds for the entry's XELT
     const TabRec* ptab;     // [sum n_j] tabulated-inverse records, packed like pent (table mode), or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base

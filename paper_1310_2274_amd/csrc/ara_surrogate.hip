@@ -471,13 +471,23 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                 for (int b0 = 0; b0 < total; b0 += 64) {
                     const int q = b0 + lane;
                     const bool in = q < total;
-                    bool is_sur = false, pol = false;
+                    bool is_sur = false, pol = false, keep = in;
                     if (in) {
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
+                        const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        // a draw whose XELT term the quantile cannot change takes it here
+                        // (term_thresholds): no network and no exact inverse
+                        const half2_t th = L.pthr[pi];
                         const SurEntry SE = L.psur[pi];
-                        if (SE.f0 >= flo && SE.f0 <= fhi && SE.f1 >= flo && SE.f1 <= fhi) {
-                            const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
+                        if (z <= (double)(float)th.x) {
+                            QV[q] = 0.0f;
+                            keep = false;
+                        } else if (z >= (double)(float)th.y) {
+                            const float4 jt = L.jt[j];
+                            QV[q] = jt.z * jt.y;
+                            keep = false;
+                        } else if (SE.f0 >= flo && SE.f0 <= fhi && SE.f1 >= flo && SE.f1 <= fhi) {
                             // Phi^-1 of the draw from its tail code (1 - z formed in FP64 for correlated draws)
                             const float zc = tail_code(z);
                             const float v = zc > 0.0f ? normcdfinvf(zc) : -normcdfinvf(-zc);
@@ -489,11 +499,11 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                             pol = fmin(E.a, E.b) < kPolishShapeEntry;
                         }
                     }
-                    const uint64_t bs = __ballot(in && is_sur);
-                    const uint64_t bf = __ballot(in && !is_sur && !pol);
-                    const uint64_t bp = __ballot(in && pol);
+                    const uint64_t bs = __ballot(keep && is_sur);
+                    const uint64_t bf = __ballot(keep && !is_sur && !pol);
+                    const uint64_t bp = __ballot(keep && pol);
                     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                    if (in) {
+                    if (keep) {
                         if (is_sur) LS[ns + __popcll(bs & below)] = (uint16_t)q;
                         else if (pol) LP[np + __popcll(bp & below)] = (uint16_t)q;
                         else LF[nf + __popcll(bf & below)] = (uint16_t)q;
