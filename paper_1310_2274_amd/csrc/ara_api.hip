@@ -396,7 +396,7 @@ size_t table_bytes(int mode, int32_t C, const LayerPlan& p, int32_t kind)
         b += align256(slots * 32);
     }
     if (p.has_corr) b += align256(p.total * 8);
-    if (mode != ARA_MODE_MEAN) b += align256(p.total * 4);
+    if (mode != ARA_MODE_MEAN) b += align256(p.total * sizeof(TermThr));
     if (mode == ARA_MODE_PLAIN) b += align256(p.total * sizeof(SolveRec));
     if (mode == ARA_MODE_TABLE) b += align256(p.total * sizeof(TabRec));
     if (mode == ARA_MODE_SURROGATE) b += align256(p.total * sizeof(SurEntry));
@@ -435,8 +435,8 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         psol = (SolveRec*)q;
         q += align256(p.total * sizeof(SolveRec));
     }
-    half2_t* pthr = (half2_t*)q;           // every sampling mode
-    q += align256(p.total * 4);
+    TermThr* pthr = (TermThr*)q;           // every sampling mode
+    q += align256(p.total * sizeof(TermThr));
     HIPCHK(c, launch_layer_count(C, J, elts_dev, rows, cnt, s));
     HIPCHK(c, launch_exclusive_scan(cnt, off, C, scr, s));
     TabRec* ptab = nullptr;

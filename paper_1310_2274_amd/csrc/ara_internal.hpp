@@ -43,7 +43,7 @@ struct LayerDev {
     const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
     const float2* pcw;      // [sum n_j] combine weights, or null
     const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
-    const half2_t* pthr;    // [sum n_j] sampling modes: (lo, hi) of term_thresholds for the entry's XELT
+    const TermThr* pthr;    // [sum n_j] sampling modes: term_thresholds for the entry's XELT
     const TabRec* ptab;     // [sum n_j] tabulated-inverse records, packed like pent (table mode), or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
@@ -77,7 +77,7 @@ hipError_t launch_layer_count(int32_t C, int32_t J, const EltDev* elts, uint4* r
 size_t scan_scratch_words(int64_t n);
 hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* scratch, hipStream_t s);
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, SolveRec* psol, half2_t* pthr, TabRec* ptab,
+                             EntryRec* pent, float2* pcw, SolveRec* psol, TermThr* pthr, TabRec* ptab,
                              hipStream_t s);
 hipError_t launch_elt_tab(int32_t n, const EntryRec* ent, TabRec* tab, hipStream_t s);
 hipError_t launch_layer_hash(int32_t C, const uint4* rows, uint4* slots, uint32_t hbits, hipStream_t s);

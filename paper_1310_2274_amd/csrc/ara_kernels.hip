@@ -108,7 +108,7 @@ __global__ void k_layer_count(int32_t C, int32_t J, const EltDev* __restrict__ e
 
 __global__ void k_layer_fill(int32_t C, int32_t J, const EltDev* __restrict__ elts, const uint32_t* __restrict__ off,
                              uint4* __restrict__ rows, EntryRec* __restrict__ pent, float2* __restrict__ pcw,
-                             SolveRec* __restrict__ psol, half2_t* __restrict__ pthr, TabRec* __restrict__ ptab)
+                             SolveRec* __restrict__ psol, TermThr* __restrict__ pthr, TabRec* __restrict__ ptab)
 {
     const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= C) return;
@@ -501,11 +501,11 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         if (SKIP) {
                             // the loss would lie within the retention, or beyond
                             // retention + limit: the term is 0 or the limit
-                            const half2_t th = L.pthr[pi];
-                            if (zc <= (double)(float)th.x) {
+                            const TermThr th = L.pthr[pi];
+                            if (zc <= (double)thr_lo(th)) {
                                 QV[q] = 0.0f;
                                 keep = false;
-                            } else if (zc >= (double)(float)th.y) {
+                            } else if (zc >= (double)thr_hi(th)) {
                                 const float4 jt = L.jt[j];
                                 QV[q] = jt.z * jt.y;
                                 keep = false;
@@ -1159,7 +1159,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
 }
 
 hipError_t launch_layer_fill(int32_t C, int32_t J, const EltDev* elts, const uint32_t* off, uint4* rows,
-                             EntryRec* pent, float2* pcw, SolveRec* psol, half2_t* pthr, TabRec* ptab,
+                             EntryRec* pent, float2* pcw, SolveRec* psol, TermThr* pthr, TabRec* ptab,
                              hipStream_t s)
 {
     hipLaunchKernelGGL(k_layer_fill, dim3(nblocks(C, 256)), dim3(256), 0, s, C, J, elts, off, rows, pent, pcw, psol,

@@ -158,47 +158,28 @@ __host__ __device__ inline double beta_inc(double t, const EntryRec& E)
     return t <= ts ? beta_inc_lower(t, E.a, E.b, E.lnB) : 1.0 - beta_inc_lower(1.0 - t, E.b, E.a, E.lnB);
 }
 
-// float(v) rounded toward -inf / +inf.
-__host__ __device__ inline float f32_down(double v)
-{
-    const float f = (float)v;
-    return (double)f > v ? nextafterf(f, -INFINITY) : f;
-}
-__host__ __device__ inline float f32_up(double v)
-{
-    const float f = (float)v;
-    return (double)f < v ? nextafterf(f, INFINITY) : f;
-}
-
-// half(v) rounded toward 0 / +inf, for 0 <= v <= 2 (a step of one in the
-// bit pattern is one unit in the last place for non-negative halves).
-__host__ __device__ inline _Float16 f16_down(float v)
-{
-    const _Float16 h = (_Float16)v;
-    return (float)h > v ? __builtin_bit_cast(_Float16, (uint16_t)(__builtin_bit_cast(uint16_t, h) - 1u)) : h;
-}
-__host__ __device__ inline _Float16 f16_up(float v)
-{
-    const _Float16 h = (_Float16)v;
-    return (float)h < v ? __builtin_bit_cast(_Float16, (uint16_t)(__builtin_bit_cast(uint16_t, h) + 1u)) : h;
-}
+// Term thresholds of one packed entry in 16 bits: lo and hi as 8-bit codes
+// in steps of 1/255.  thr_lo <= lo and thr_hi >= hi hold with a relative
+// margin of 1e-6, far above the rounding of the float decode, so
+// z <= thr_lo implies z <= lo and z >= thr_hi implies z >= hi.  A code of 255
+// decodes to 1: as lo it skips every draw (z < 1), as hi none.
+typedef uint16_t TermThr;
+__host__ __device__ inline float thr_lo(TermThr t) { return (float)(t & 0xFFu) * (1.0f / 255.0f); }
+__host__ __device__ inline float thr_hi(TermThr t) { return (float)(t >> 8) * (1.0f / 255.0f); }
 
 // The draws of an entry whose per-XELT term does not depend on the quantile
 // (section 2.3's financial terms I on the sampled loss of section 3.3): a
 // loss l = max_l x at most the retention nets to 0, one at least retention +
-// limit nets to the limit, and x <= t  <=>  z <= I_t(alpha, beta).  Returns
-// (lo, hi) in half precision: z <= lo gives 0, z >= hi the limit.  Both come
-// from FP64 probabilities, widened by 1e-10 relative (far above their
-// rounding) and rounded outward, so a draw is skipped only where its loss
-// certainly lies beyond the threshold; draws inside the margin (at most one
-// half-precision step, 2^-11 relative) are solved.  lo = 0 and hi = 2 never
-// skip (z > 0 and z < 1 on the uniform grid; a correlated z of exactly 0 has
-// x = 0); lo = 1 and hi = 0 always do.  A degenerate entry's loss is its mean
-// (lnB): always one side or never.  Four bytes per entry keep the table small
-// enough to stay in L2 beside the layer rows.
-__host__ __device__ inline half2_t term_thresholds(const EntryRec& E, double ret, double lim)
+// limit nets to the limit, and x <= t  <=>  z <= I_t(alpha, beta).  From the
+// FP64 probabilities lo = I_{ret/max_l} and hi = I_{(ret+lim)/max_l},
+// widened by 1e-10 relative (far above their rounding) and coded outward, a
+// draw is skipped only where its loss certainly lies beyond a threshold; the
+// draws within one code step (1/255) of it are solved.  A degenerate
+// entry's loss is its mean (lnB): always one side or never.  Two bytes per
+// entry keep the table small enough to stay in L2 beside the layer rows.
+__host__ __device__ inline TermThr term_thresholds(const EntryRec& E, double ret, double lim)
 {
-    double lo = 0.0, hi = 2.0;
+    double lo = 0.0, hi = 2.0;                         // never: z > 0 and z < 1
     if (E.a == 0.0) {
         if (E.lnB <= ret) lo = 1.0;
         else if (E.lnB >= ret + lim) hi = 0.0;
@@ -212,10 +193,9 @@ __host__ __device__ inline half2_t term_thresholds(const EntryRec& E, double ret
             hi = I + (1.0 - I) * 1e-10;
         }
     }
-    half2_t r;
-    r.x = f16_down(f32_down(lo));
-    r.y = f16_up(f32_up(hi));
-    return r;
+    const uint32_t cl = lo >= 1.0 ? 255u : (uint32_t)floor(lo * 255.0 * (1.0 - 1e-6));
+    const uint32_t ch = hi <= 0.0 ? 0u : hi >= 1.0 ? 255u : (uint32_t)fmin(ceil(hi * 255.0 * (1.0 + 1e-6)), 255.0);
+    return (TermThr)(cl | (ch << 8));
 }
 
 // ---------------------------------------------------------------------------

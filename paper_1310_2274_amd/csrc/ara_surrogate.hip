@@ -478,12 +478,12 @@ __global__ __launch_bounds__(64 * WPB) void k_layer_surrogate(YetDev y, int64_t 
                         const double z = sur_draw_z<HAS_CORR>(tr, slot, j, L.seed, L.prog, L.pcw, pi);
                         // a draw whose XELT term the quantile cannot change takes it here
                         // (term_thresholds): no network and no exact inverse
-                        const half2_t th = L.pthr[pi];
+                        const TermThr th = L.pthr[pi];
                         const SurEntry SE = L.psur[pi];
-                        if (z <= (double)(float)th.x) {
+                        if (z <= (double)thr_lo(th)) {
                             QV[q] = 0.0f;
                             keep = false;
-                        } else if (z >= (double)(float)th.y) {
+                        } else if (z >= (double)thr_hi(th)) {
                             const float4 jt = L.jt[j];
                             QV[q] = jt.z * jt.y;
                             keep = false;
