@@ -445,13 +445,13 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         q += align256(p.total * sizeof(TabRec));
     }
     HIPCHK(c, launch_layer_fill(C, J, elts_dev, off, rows, pent, pcw, psol, pthr, ptab, s));
-    p.dev.rows = rows;
+    p.dev.rows = gptr(rows);
     p.dev.hbits = 0;
-    p.dev.pent = pent;
-    p.dev.pcw = pcw;
-    p.dev.psol = psol;
-    p.dev.pthr = pthr;
-    p.dev.ptab = ptab;
+    p.dev.pent = gptr(pent);
+    p.dev.pcw = gptr(pcw);
+    p.dev.psol = gptr(psol);
+    p.dev.pthr = gptr(pthr);
+    p.dev.ptab = gptr(ptab);
     if (mode == ARA_MODE_SURROGATE) {
         SurEntry* psur = (SurEntry*)q;
         q += align256(p.total * sizeof(SurEntry));
@@ -465,7 +465,7 @@ ara_status build_tables(ara_ctx* c, int mode, int32_t C, LayerPlan& p, char* bas
         uint4* hs = (uint4*)q;
         q += align256(slots * 32);
         HIPCHK(c, launch_layer_hash(C, rows, hs, bits, s));
-        p.dev.rows = hs;
+        p.dev.rows = gptr(hs);
         p.dev.hbits = bits;
     }
     return ARA_OK;

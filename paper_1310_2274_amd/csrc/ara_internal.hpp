@@ -34,17 +34,28 @@ struct EltDev {
 constexpr int kRowPolBits = 25;
 __host__ __device__ inline int row_count(uint32_t w) { return (int)(w & 127u); }
 
+// The device compile marks the layer tables' pointers as global memory, so
+// the kernels gather through global (not flat) loads, which leave the LDS
+// counter alone; host code stores them through gptr().
+#ifdef __HIP_DEVICE_COMPILE__
+#define ARA_GLOBAL __attribute__((address_space(1)))
+#else
+#define ARA_GLOBAL
+#endif
+template <typename T>
+inline const ARA_GLOBAL T* gptr(const T* p) { return (const ARA_GLOBAL T*)p; }
+
 // One layer of a run: its tables (built per run on the device) and terms.
 struct LayerDev {
-    const uint4* rows;      // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count | flags},
+    const ARA_GLOBAL uint4* rows;   // [C] {mask bits 0-31, mask bits 32-63, first packed entry, count | flags},
                             // or, when hbits > 0, 2^hbits hash slots of two uint4 each:
                             // {event id (-1 empty), mask bits 0-31, mask bits 32-63, first entry}, {count | flags}
     uint32_t hbits;         // log2 of the hashed table's slot count; 0 = direct access
-    const EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
-    const float2* pcw;      // [sum n_j] combine weights, or null
-    const SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
-    const TermThr* pthr;    // [sum n_j] sampling modes: term_thresholds for the entry's XELT
-    const TabRec* ptab;     // [sum n_j] tabulated-inverse records, packed like pent (table mode), or null
+    const ARA_GLOBAL EntryRec* pent;   // [sum n_j] entries packed by event, in the layer's XELT order
+    const ARA_GLOBAL float2* pcw;      // [sum n_j] combine weights, or null
+    const ARA_GLOBAL SolveRec* psol;   // [sum n_j] solve records, packed like pent (plain mode), or null
+    const ARA_GLOBAL TermThr* pthr;    // [sum n_j] sampling modes: term_thresholds for the entry's XELT
+    const ARA_GLOBAL TabRec* ptab;     // [sum n_j] tabulated-inverse records, packed like pent (table mode), or null
     const float* occ_tab;   // [C] mean mode: per-event loss net of I and occurrence terms
     const SurEntry* psur;   // [sum n_j] surrogate mode: per-entry features and base
     float* ylt;             // [trial_end - trial_begin]
