@@ -542,15 +542,25 @@ def main():
     if pc["current"] and N == 800_000 and "fetch_kib_per_launch" in pc:
         traffic = (float(pc["fetch_scale"]) * float(pc["fetch_kib_per_launch"]) +
                    float(pc["write_scale"]) * float(pc["write_kib_per_launch"])) * 1024
-    roof = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-            "frac": ach / PEAK_VALU_TOPS if ach else None, "traffic": traffic,
+    # Algorithmic bytes per launch (the units of the plain path's gathers): the
+    # YET's 4-byte ids, one 16-byte layer-table row per trial-event, the
+    # entry's 16 bytes of Beta parameters per draw, and the 4-byte YLT.
+    te = float(N) * float(wl.events_per_trial)
+    alg_bytes = 4.0 * te + 16.0 * te + 16.0 * draws + 4.0 * N
+    ach_gbs = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach_gbs / PEAK_HBM_GBS, "traffic": traffic,
             "kernel": "k_layer_plain", "kernel_ms": kernel_ms, "draws_per_launch": draws,
-            "draws_per_s": draws / (kernel_ms * 1e-3), "ops_per_draw": opd,
-            "ops_unit": "VALU lane-instructions (SQ_INSTS_VALU x 64 / draws)",
+            "draws_per_s": draws / (kernel_ms * 1e-3), "algorithmic_bytes": alg_bytes,
             "counters_match_kernel_sources": pc["current"],
-            "valu_busy": float(pc["valu_busy"]) if "valu_busy" in pc else None,
-            "note": "peak = one wave64 VALU instruction per SIMD per 4 cycles; part of the stream issues on "
-                    "the second VALU pipe (SQ_ACTIVE_INST_VALU2), so the counted rate can exceed it"}
+            "alu_view": {"ops_per_draw": opd, "ops_unit": "VALU lane-instructions (SQ_INSTS_VALU x 64 / draws)",
+                         "achieved_TOPs": ach, "peak_TOPs": PEAK_VALU_TOPS,
+                         "valu_busy": float(pc["valu_busy"]) if "valu_busy" in pc else None},
+            "note": "algorithmic bytes: 4 B (YET id) + 16 B (layer row) per trial-event, 16 B (Beta parameters) "
+                    "per draw, 4 B per trial; traffic: L2 <-> fabric bytes from FETCH_SIZE/WRITE_SIZE. The "
+                    "launch is bound by L1 misses in flight (about 62 per CU, 410-cycle average L2 latency, "
+                    "texture data unit busy 0.98: profiles/k_layer_plain_paper800k_memory.md), not by VALU "
+                    "issue: removing the solve arithmetic or 6 of the 10 Philox rounds saves little"}
 
     mean_leg = None
     if not args.no_mean_leg:
