@@ -315,7 +315,6 @@ template <bool HAS_CORR, int WPB, bool TAB>
 __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB == 8 ? 3 : 5))) void k_layer_plain(YetDev y, int64_t t0, int64_t t1,
                                                           const LayerDev* __restrict__ layers, int32_t n_layers)
 {
-    constexpr bool SKIP = true;      // draws whose term is fixed skip the inverse (term_thresholds), in both modes
     __shared__ uint32_t qidx[WPB][kQueue];
     __shared__ uint16_t qmeta[WPB][kQueue];
     __shared__ float qv[WPB][kQueue];
@@ -494,22 +493,18 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                         const uint32_t pi = QI[q], meta = QM[q];
                         const uint32_t own = meta & 63u, j = meta >> 8;
                         pol = (meta & 0x80u) != 0u;
-                        if (HAS_CORR)
-                            zc = corr_z(tr, (uint32_t)base + own, j, L.seed, L.prog, L.pcw, pi, UC[own], QC[own]);
-                        else if (SKIP)
-                            zc = draw_z<false>(tr, (uint32_t)base + own, j, L.seed, L.prog, nullptr, pi);
-                        if (SKIP) {
-                            // the loss would lie within the retention, or beyond
-                            // retention + limit: the term is 0 or the limit
-                            const TermThr th = L.pthr[pi];
-                            if (zc <= (double)thr_lo(th)) {
-                                QV[q] = 0.0f;
-                                keep = false;
-                            } else if (zc >= (double)thr_hi(th)) {
-                                const float4 jt = L.jt[j];
-                                QV[q] = jt.z * jt.y;
-                                keep = false;
-                            }
+                        zc = HAS_CORR ? corr_z(tr, (uint32_t)base + own, j, L.seed, L.prog, L.pcw, pi, UC[own], QC[own])
+                                      : draw_z<false>(tr, (uint32_t)base + own, j, L.seed, L.prog, nullptr, pi);
+                        // the loss would lie within the retention, or beyond retention +
+                        // limit (term_thresholds): the term is 0 or the limit, no solve
+                        const TermThr th = L.pthr[pi];
+                        if (zc <= (double)thr_lo(th)) {
+                            QV[q] = 0.0f;
+                            keep = false;
+                        } else if (zc >= (double)thr_hi(th)) {
+                            const float4 jt = L.jt[j];
+                            QV[q] = jt.z * jt.y;
+                            keep = false;
                         }
                     }
                     const uint64_t b64 = __ballot(keep && pol);
@@ -524,8 +519,9 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                             QV[q] = kDeferred;
                         } else {
                             L32[n32 + __popcll(b32 & below)] = (uint16_t)q;
-                            if (HAS_CORR) QV[q] = tail_code(zc);      // the FP32 solve takes z as its tail code
-                            else if (SKIP) QV[q] = (float)zc;         // on the 2^-24 grid: exact
+                            // the FP32 solve takes z as its tail code (uncorrelated draws are
+                            // on the 2^-24 grid, where the code is z itself, exactly)
+                            QV[q] = HAS_CORR ? tail_code(zc) : (float)zc;
                         }
                     }
                     n32 = __builtin_amdgcn_readfirstlane(n32 + __popcll(b32));
@@ -560,11 +556,10 @@ __global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(WPB ==
                     const int idx = b0 + lane;
                     if (idx < n32) {
                         const int q = L32[idx];
-                        const uint32_t pi = QI[q], meta = QM[q];
-                        const uint32_t slot = (uint32_t)base + (meta & 63u), j = meta >> 8;
-                        // uncorrelated draws are on the 2^-24 grid; correlated ones arrive as tail codes
-                        const float z = (HAS_CORR || SKIP) ? QV[q]
-                                                           : (float)draw_z<false>(tr, slot, j, L.seed, L.prog, nullptr, pi);
+                        const uint32_t pi = QI[q], j = QM[q] >> 8;
+                        // the draw's z from the classify pass (uncorrelated draws are on the
+                        // 2^-24 grid; correlated ones arrive as tail codes)
+                        const float z = QV[q];
                         float loss;
                         if (TAB) {
                             const TabRec& T = L.ptab[pi];
