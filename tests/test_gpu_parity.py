@@ -556,8 +556,8 @@ def _fixed_shape_elt(rng, C, n, a, b, q_lo, q_hi, sigma_c_frac=0.0, degenerate=N
     return synth.ELT(ids, mu, sd, sc, mx, ded, top - ded, 0.75)
 
 
-@pytest.mark.parametrize("sigma_c_frac", [0.0, 0.4])
-def test_fixed_term_draws_vs_oracle(eng, sigma_c_frac):
+@pytest.mark.parametrize("mode,sigma_c_frac", [("plain", 0.0), ("plain", 0.4), ("table", 0.0), ("table", 0.4)])
+def test_fixed_term_draws_vs_oracle(eng, mode, sigma_c_frac):
     # XELT terms at entry quantiles: in the plain mode a draw whose loss lies
     # within the retention or beyond retention + limit takes its term without
     # the inverse (term_thresholds); the year and occurrence losses must match
@@ -578,8 +578,15 @@ def test_fixed_term_draws_vs_oracle(eng, sigma_c_frac):
         _fixed_shape_elt(rng, C, 300, 2.0, 5.0, 0.2, 0.9, degenerate=3e5),      # mean between
     ]
     lay.occ_retention, lay.occ_limit, lay.agg_retention, lay.agg_limit = 0.0, math.inf, 0.0, math.inf
-    y, om, _ = gpu_ylt(eng, wl, oracle.MODE_PLAIN, 19, with_omax=True)
+    y, om, _ = gpu_ylt(eng, wl, P.MODE_PLAIN if mode == "plain" else P.MODE_TABLE, 19, with_omax=True)
     yo, g, omo = oracle_ylt(wl, np.arange(N), oracle.MODE_PLAIN, 19)
-    assert_ylt_close(y, yo, g, f"fixed-term draws, sigma_c_frac={sigma_c_frac}")
-    assert_ylt_close(om, omo, g, "max occurrence")
+    if mode == "plain":
+        assert_ylt_close(y, yo, g, f"fixed-term draws, sigma_c_frac={sigma_c_frac}")
+        assert_ylt_close(om, omo, g, "max occurrence")
+    else:
+        # the tabulated inverse is within 2e-4 relative per draw (its own tests),
+        # and every term is 1-Lipschitz: a year or occurrence loss moves by at
+        # most 2e-4 of the trial's gross
+        tol = 2e-4 * g + 1e-3
+        assert np.all(np.abs(y - yo) <= tol) and np.all(np.abs(om - omo) <= tol)
     assert np.all(y > 0)
