@@ -134,7 +134,11 @@ typedef struct {
  * u_C = U(Philox4x32-10(key (seed, 0xFFFFFFFF), counter (trial, slot,
  * 0xFFFFFFFF, 1))), first output word, U(w) = (2*(w>>9)+1)*2^-24.
  * The result is a deterministic function of the inputs and seed: it does not
- * depend on the stream, launch shape or what else runs on the device.
+ * depend on the stream, launch shape or what else runs on the device.  In the
+ * sampling modes a draw whose loss would lie within its XELT's retention or
+ * beyond retention + limit takes its term (0 or the limit) from the entry's
+ * term thresholds, without the inverse: the year losses are those of
+ * inverting every draw, up to the inverse's own rounding.
  * max_occ_out (optional, NULL to skip) receives the largest occurrence loss
  * net of occurrence terms per trial (the occurrence exceedance basis).
  */
